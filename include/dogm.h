@@ -1,0 +1,202 @@
+/*
+ * dogm.h - C ABI of the MI355X (gfx950) implementation of the per-cycle particle recursion of
+ * the Dempster-Shafer PHD/MIB dynamic occupancy grid filter (Nuss et al., "A Random Finite Set
+ * Approach for Dynamic Occupancy Grid Maps with Real-Time Application", arXiv 1605.02406,
+ * Sec. VI and the parallel form of Sec. VII, Algorithms 1-7).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Memory.   The library never allocates device memory.  One grid lives entirely inside one
+ *           caller-owned device buffer (the "arena", size from dogm_arena_bytes).  The arena
+ *           must stay allocated and must not be touched by the caller while the grid exists,
+ *           except through the arrays that dogm_view exposes.  The grid handle itself is a
+ *           small host object owned by the library (freed by dogm_destroy).
+ * Streams.  Every call only enqueues kernels on the grid's HIP stream and returns without
+ *           synchronising; results are visible to work ordered after it on that stream.  No
+ *           call reads device memory back to the host, so a cycle can be captured in a HIP
+ *           graph.  Calls on one grid must not overlap from several host threads.
+ * Errors.   Every call returns an int: DOGM_OK (0) or a negative code below.  A failed call
+ *           enqueues nothing (argument and state checks) or reports the launch error of HIP
+ *           (DOGM_EHIP, text from dogm_last_error).  Numeric anomalies found on the device
+ *           set bits of the device status word (DOGM_ST_*), readable through dogm_view.
+ * Order.    init -> per cycle: predict, assign, update, [moments], resample (or step).  A call
+ *           out of this order returns DOGM_ESTATE and enqueues nothing.
+ * Layout.   Cells are row-major, cell = iy*nx + ix, origin at the grid corner; x spans
+ *           [0, nx*cell_size), y spans [0, ny*cell_size).  Particles are structure-of-arrays
+ *           FP32 (x, y, vx, vy, w).  Key C (= nx*ny) marks a particle outside the grid.
+ */
+#ifndef DOGM_H
+#define DOGM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* A hipStream_t, passed as an opaque pointer (NULL = the null stream). */
+typedef void* dogm_stream_t;
+
+typedef struct dogm_grid dogm_grid;
+
+enum {
+    DOGM_OK = 0,
+    DOGM_EINVAL = -1,  /* bad pointer, parameter or size                            */
+    DOGM_ESIZE = -2,   /* arena too small                                          */
+    DOGM_EHIP = -3,    /* a HIP call or kernel launch failed                       */
+    DOGM_ESTATE = -4,  /* call out of order                                        */
+    DOGM_ENOTIMPL = -5 /* not available in this build                              */
+};
+
+/* Device status word bits. */
+enum {
+    DOGM_ST_CONFLICT = 1u,  /* Dempster total conflict (1-K < 1e-12): prediction kept  */
+    DOGM_ST_NOCARRIER = 2u, /* a cell with new-born mass received no new-born slot     */
+    DOGM_ST_NONFINITE = 4u, /* a non-finite mass or weight was met                     */
+    DOGM_ST_INTERNAL = 8u   /* an internal consistency check failed (library bug)      */
+};
+
+/* Filter parameters (Table I and the process model of eq. (process)). */
+typedef struct dogm_params {
+    int32_t nx, ny;        /* cells along x and y, 1 <= nx, ny; nx*ny < 2^26               */
+    float cell_size;       /* cell edge r [m], > 0                                          */
+    float dt;              /* time step T [s]                                               */
+    float p_s;             /* persistence probability p_S, eq. (particle_persistence)       */
+    float p_b;             /* birth probability p_B, eq. (predicted_ex_born)                */
+    float sigma_pos;       /* process-noise SD on position per step [m]                     */
+    float sigma_vel;       /* process-noise SD on velocity per step [m/s]                   */
+    float sigma_birth_vel; /* SD of new-born velocity sigma_B,v [m/s] (Table I)             */
+    float alpha_free;      /* free-mass discount alpha(T) in [0,1], eq. (DS_freespace_pred) */
+    int64_t n_pers;        /* persistent particles nu, 1 <= nu < 2^30                       */
+    int64_t n_born;        /* new-born slots nu_b, 0 <= nu_b < 2^30                         */
+    uint64_t seed;         /* Philox4x32-10 key                                            */
+    uint32_t grid_id;      /* fourth Philox counter word: separates grids with one seed     */
+    uint32_t reserved;     /* must be 0                                                     */
+} dogm_params;
+
+/* One measurement grid (Sec. VI.C): device pointers to C floats each, read only during the
+ * dogm_update / dogm_step call's kernels.  m_occ, m_free: the observed BBA m_z(O), m_z(F)
+ * with m_occ + m_free <= 1 (required).  p_assoc: association probability p_A per cell, or
+ * NULL for p_A = 0 everywhere; when given, mu_vx, mu_vy, var_v (measured velocity and its
+ * variance, > 0) define the spatial likelihood g(z|x) = N(v; mu, var I) and the associated
+ * new-born velocity pdf, and must be non-NULL. */
+typedef struct dogm_meas {
+    const float* m_occ;
+    const float* m_free;
+    const float* p_assoc;
+    const float* mu_vx;
+    const float* mu_vy;
+    const float* var_v;
+} dogm_meas;
+
+/* Device pointers to every array of a grid (all inside the arena). */
+typedef struct dogm_views {
+    /* persistent particles at the start of a cycle / after resampling (nu each) */
+    float *x, *y, *vx, *vy, *w;
+    uint32_t* key;        /* cell key written by predict, in the order of x..w (nu)          */
+    /* particles sorted by cell (after assign; update rewrites w) (nu each) */
+    float *sx, *sy, *svx, *svy, *sw;
+    uint32_t* skey;       /* sorted keys (nu)                                               */
+    uint32_t* perm;       /* sorted position -> index in x..w (nu)                          */
+    /* cells (C each unless noted) */
+    uint32_t *cell_start, *cell_end; /* particle range [start, end) of each cell in sorted order */
+    double* sum_w;        /* sum of predicted persistent weights (FP64; 0 for empty cells) */
+    float *m_pO, *m_pF;   /* predicted BBA                                                  */
+    float *m_O, *m_F;     /* posterior BBA; m_F is also the state carried to the next cycle  */
+    float *rho_b, *rho_p; /* new-born / persistent part of m_O                              */
+    float* pign;          /* pignistic occupancy probability                                */
+    double *mu_A, *mu_UA; /* normalisation components of the persistent update               */
+    uint32_t* born_off;   /* new-born slot range [born_off[c], born_off[c+1]) (C+1)          */
+    float *mean_x, *mean_y, *var_x, *var_y, *cov_xy; /* velocity moments                     */
+    uint8_t* mom_flag;    /* 1 where the moments are defined (rho_p > 0 and particles)       */
+    /* new-born particles of the last update (nu_b each) */
+    float *bx, *by, *bvx, *bvy, *bw;
+    uint32_t* bkey;
+    uint8_t* bassoc;      /* 1 for associated new-born particles                            */
+    /* device scalars */
+    uint32_t* status;     /* DOGM_ST_* bits, sticky                                          */
+    uint32_t* cycle;      /* cycle counter used by the random streams                        */
+    uint64_t* W_fixed;    /* joint posterior weight of the last resampling, units 2^-40      */
+    uint64_t* S_fixed;    /* total new-born mass of the last update, units 2^-40            */
+    int64_t n_pers, n_born, n_cells;
+} dogm_views;
+
+/* Bytes of device memory one grid with these parameters needs.  DOGM_EINVAL on bad params. */
+int dogm_arena_bytes(const dogm_params* params, size_t* bytes);
+
+/* Creates a grid inside `arena` (device memory, >= dogm_arena_bytes bytes, 256-byte aligned)
+ * and enqueues its initial state on `stream`: nu particles uniform over the grid, velocity
+ * N(0, sigma_B^2 I), weight 0; m_F = 0; status 0; cycle counter 1.  (The paper leaves the
+ * initial state open.)  *out receives the handle.  DOGM_EINVAL / DOGM_ESIZE / DOGM_EHIP. */
+int dogm_init_grid(const dogm_params* params, void* arena, size_t arena_bytes,
+                   dogm_stream_t stream, dogm_grid** out);
+
+/* Frees the host handle (the arena stays the caller's).  Waits for nothing. */
+int dogm_destroy(dogm_grid* grid);
+
+/* Changes the stream later calls enqueue on. */
+int dogm_set_stream(dogm_grid* grid, dogm_stream_t stream);
+
+/* Sets the cycle counter (device and host copy, enqueued on the grid's stream) and makes
+ * predict the next valid call.  For tests and for replaying a cycle from saved state. */
+int dogm_set_cycle(dogm_grid* grid, uint32_t cycle);
+
+/* Host copy of the cycle counter. */
+int dogm_get_cycle(const dogm_grid* grid, uint32_t* cycle);
+
+/* Device pointers of every array (valid for the lifetime of the grid). */
+int dogm_view(const dogm_grid* grid, dogm_views* views);
+
+/* Alg. 1, eqs. (process) and (particle_persistence): in place on x..w, per particle
+ * x' = x + T vx + sigma_pos n1, y' = y + T vy + sigma_pos n2, vx' = vx + sigma_vel n3,
+ * vy' = vy + sigma_vel n4, w' = p_S w, with standard normals from Philox counter
+ * (index, cycle, 1, grid_id); writes the cell key (C and w' = 0 outside the grid). */
+int dogm_predict(dogm_grid* grid);
+
+/* Alg. 2: stable sort of the particles by cell key into sx..sw / skey / perm, and the
+ * particle range of every cell (cell_start, cell_end; empty cells have start == end). */
+int dogm_assign(dogm_grid* grid);
+
+/* Alg. 3, 4 and 5 in the paper's order:
+ *  - per cell: m_p(O) = min(sum w, 1), m_p(F) = min(alpha m_F, 1 - m_p(O)),
+ *    (m_O, m_F) = m_p (+) m_z (Dempster), rho_b / rho_p split of eq. (DS_resulting_masses1/2)
+ *    (new-born mass only where m_z(O) > 0);
+ *  - persistent weights: w <- p_A mu_A g w + (1 - p_A) mu_UA w, eq. (DSnormalization);
+ *  - new-born particles: nu_b slots allocated in proportion to rho_b, split into associated /
+ *    unassociated sets, uniform position in the cell, velocity from p(x|z) or N(0, sigma_B^2),
+ *    weights of eqs. (weights_associated), (weights_unassociated).
+ * `meas` is a host struct of device pointers (see dogm_meas).  DOGM_EINVAL if m_occ/m_free is
+ * NULL or p_assoc is given without mu_vx/mu_vy/var_v. */
+int dogm_update(dogm_grid* grid, const dogm_meas* meas);
+
+/* Alg. 6, eqs. (mean_x), (var_x), (covar_xy): velocity mean, variance and covariance of the
+ * updated persistent particles of every cell, normalised by rho_p; zeros and mom_flag 0
+ * where rho_p <= 0 or the cell holds no particle. */
+int dogm_moments(dogm_grid* grid);
+
+/* Alg. 7, eq. (resampledParticleWeights): systematic resampling of nu particles from the joint
+ * set [sorted persistent | new-born] into x..w, every weight W/nu with W the joint weight;
+ * draws u_j = (j + U) W / nu with U from Philox counter (0, cycle, 3, grid_id).  With W = 0
+ * the sorted persistent set is kept.  Advances the cycle counter. */
+int dogm_resample(dogm_grid* grid);
+
+/* predict, assign, update, moments, resample in order (one full cycle). */
+int dogm_step(dogm_grid* grid, const dogm_meas* meas);
+
+/* One full cycle of n independent grids, each kernel launched once for all of them (grids of
+ * different sizes share every launch).  All grids must have completed the same phase (ready
+ * for predict); all work is enqueued on `stream`.  meas[i] belongs to grids[i].  The result of
+ * every grid is bit-identical to dogm_step on that grid alone. */
+int dogm_step_batch(dogm_grid* const* grids, const dogm_meas* meas, int n,
+                    dogm_stream_t stream);
+
+/* Text of a status code, or of the last DOGM_EHIP error of the calling thread. */
+const char* dogm_status_string(int code);
+const char* dogm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DOGM_H */

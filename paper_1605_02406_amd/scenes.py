@@ -129,6 +129,7 @@ def _place_boxes(rng, nx, ny, cell, sizes, vels, keepout=3.0, tries=2000):
     sx, sy = W / 2, H / 2
     boxes = []
     for (w, h), (vx, vy) in zip(sizes, vels):
+        w, h = min(w, 0.5 * W), min(h, 0.5 * H)  # keep every box placeable on small grids
         for _ in range(tries):
             cx = rng.uniform(w / 2, W - w / 2)
             cy = rng.uniform(h / 2, H - h / 2)

@@ -1,0 +1,212 @@
+"""Per-call parity of the HIP library against the oracle.
+
+Each C-ABI call is checked on its own: the grid's device state just before the call is copied
+to the host, the oracle runs the same step on exactly those values (FP32 widened to FP64), and
+the outputs are compared.  Downstream calls always continue from the GPU's own outputs.
+
+Tolerances (the bar for floating point; integer outputs are bit-exact):
+  predict   x, y, vx, vy : |d| <= 1e-5 * max(|ref|, 1)         w : rel 1e-6
+            key          : bit-exact against the oracle's FP32 cell decision on the GPU's
+                           FP32 position; equal to the FP64 decision except within TIE_M metres
+                           of a cell edge (ties, counted)
+  assign    perm, sorted arrays, cell ranges : bit-exact
+  update    cell masses  : |d| <= 1e-5 * |ref| + 1e-9           weights : rel 1e-5 (+1e-12)
+            slot offsets, new-born keys / association flags : bit-exact given the GPU's FP32
+            rho_b;  new-born positions, velocities : |d| <= 1e-5 * max(|ref|, 1)
+  moments   mean : |d| <= 1e-5 * max(|ref|, 1 m/s);  var, cov : |d| <= 1e-5 * (var + mean^2)
+            flags : bit-exact
+  resample  every output array bit-exact (exact fixed-point CDF on both sides)
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+import oracle
+from paper_1605_02406_amd import dogm
+
+POS_TOL = 1e-5
+W_PRED_TOL = 1e-6
+MASS_TOL = 1e-5
+W_TOL = 1e-5
+MOM_TOL = 1e-5
+
+
+def oracle_params(p: dogm.CParams) -> oracle.Params:
+    return oracle.Params(p.nx, p.ny, p.cell_size, p.dt, p.p_s, p.p_b, p.sigma_pos, p.sigma_vel,
+                         p.sigma_birth_vel, p.alpha_free, p.n_pers, p.n_born, seed=p.seed,
+                         grid_id=p.grid_id)
+
+
+def host(t: torch.Tensor) -> np.ndarray:
+    a = t.cpu().numpy()
+    return a.view(np.uint32) if a.dtype == np.int32 else a
+
+
+def u32(t: torch.Tensor) -> np.ndarray:
+    return t.cpu().numpy().view(np.uint32)
+
+
+def max_rel(got, ref, floor):
+    got = np.asarray(got, np.float64)
+    ref = np.asarray(ref, np.float64)
+    if got.size == 0:
+        return 0.0
+    return float(np.max(np.abs(got - ref) / np.maximum(np.abs(ref), floor)))
+
+
+def assert_close(name, got, ref, rel, floor):
+    err = max_rel(got, ref, floor)
+    assert err <= rel, f"{name}: max scaled error {err:.3e} > {rel:.1e}"
+    return err
+
+
+def tie_metres(p: dogm.CParams) -> float:
+    ext = max(p.nx, p.ny) * p.cell_size
+    ulp = np.spacing(np.float32(ext))
+    return float(8 * ulp + 1e-6 * (5 * p.sigma_pos + 1e-3))
+
+
+def meas_numpy(meas: dogm.Meas) -> dict:
+    return {k: (None if v is None else v.cpu().numpy().astype(np.float64))
+            for k, v in meas.t.items()}
+
+
+class PerCall:
+    """Runs one cycle of a grid call by call, checking each call against the oracle."""
+
+    def __init__(self, grid: dogm.Grid):
+        self.g = grid
+        self.p = oracle_params(grid.params)
+        self.stats = {}
+
+    def predict(self):
+        g, p = self.g, self.p
+        k = g.cycle
+        st0 = g.state()
+        g.predict()
+        torch.cuda.synchronize()
+        got = g.state()
+        key = u32(g.v["key"])
+        ref, key64 = oracle.predict(p, k, st0)
+        for c in ("x", "y", "vx", "vy"):
+            self.stats[f"predict.{c}"] = assert_close(f"predict {c}", got[c], ref[c], POS_TOL, 1.0)
+        self.stats["predict.w"] = assert_close("predict w", got["w"], ref["w"], W_PRED_TOL, 1e-30)
+        # the cell decision in the kernel's precision, on the kernel's FP32 position
+        key32 = oracle.cell_keys_f32(p, got["x"], got["y"])
+        assert np.array_equal(key, key32), "key differs from the FP32 cell decision"
+        # and the FP64 decision except at cell edges
+        r = np.float64(np.float32(p.cell_size))
+        fx, fy = ref["x"] / r, ref["y"] / r
+        dist = np.minimum(np.abs(fx - np.round(fx)), np.abs(fy - np.round(fy))) * r
+        tie = dist < tie_metres(g.params)
+        bad = (key != key64) & ~tie
+        assert not bad.any(), f"{bad.sum()} cell keys differ away from cell edges"
+        self.stats["predict.ties"] = int(((key != key64) & tie).sum())
+        return got, key
+
+    def assign(self):
+        g, p = self.g, self.p
+        st = g.state()
+        key = u32(g.v["key"])
+        g.assign()
+        torch.cuda.synchronize()
+        perm, start, end = oracle.assign(key, p.C)
+        assert np.array_equal(u32(g.v["perm"]), perm.astype(np.uint32)), "permutation"
+        assert np.array_equal(u32(g.v["skey"]), key[perm]), "sorted keys"
+        gs, ge = u32(g.v["cell_start"]), u32(g.v["cell_end"])
+        ne = end > start  # empty cells: only start == end is promised
+        assert np.array_equal(gs[ne], start[ne]), "cell starts"
+        assert np.array_equal(ge[ne], end[ne]), "cell ends"
+        assert np.array_equal(gs[~ne], ge[~ne]), "empty cells"
+        srt = g.state(sorted_=True)
+        for c in ("x", "y", "vx", "vy", "w"):
+            assert np.array_equal(srt[c], st[c][perm]), f"sorted {c}"
+
+    def update(self, meas: dogm.Meas):
+        g, p = self.g, self.p
+        k = g.cycle
+        srt = g.state(sorted_=True)
+        start, end = u32(g.v["cell_start"]), u32(g.v["cell_end"])
+        m_F_prev = host(g.v["m_F"]).copy()
+        mz = meas_numpy(meas)
+        g.update(meas)
+        torch.cuda.synchronize()
+        cu = oracle.cell_update(p, srt["w"], start, end, m_F_prev, mz["m_occ"], mz["m_free"])
+        for c in ("m_pO", "m_pF", "m_O", "m_F", "rho_b", "rho_p", "pign"):
+            self.stats[f"update.{c}"] = assert_close(f"update {c}", host(g.v[c]), cu[c],
+                                                     MASS_TOL, 1e-4)
+        ne = end > start
+        self.stats["update.sum_w"] = assert_close("update sum_w", host(g.v["sum_w"])[ne],
+                                                  cu["sum_w"][ne], 1e-12, 1e-300)
+        opt = {kk: mz[kk] for kk in ("p_assoc", "mu_vx", "mu_vy", "var_v")}
+        w_ref, _, _ = oracle.persistent_update(p.C, srt["w"], srt["vx"], srt["vy"], start, end,
+                                               cu["rho_p"], **opt)
+        w_got = host(g.v["sw"])
+        self.stats["update.w"] = assert_close("update w", w_got, w_ref, W_TOL, 1e-12)
+        # new-born particles from the GPU's own FP32 rho_b: the integer decisions are exact
+        rho_b = host(g.v["rho_b"]).astype(np.float64)
+        off, S = oracle.born_alloc(p.C, p.n_born, rho_b)
+        assert int(g.v["S_fixed"].item()) == S, "new-born mass total"
+        assert np.array_equal(u32(g.v["born_off"]), off), "new-born slot offsets"
+        b = oracle.born_init(p, k, off, rho_b, **opt)
+        assert np.array_equal(u32(g.v["bkey"]), b["key"]), "new-born keys"
+        assert np.array_equal(host(g.v["bassoc"]), b["assoc"]), "association flags"
+        for c, n in (("x", "bx"), ("y", "by"), ("vx", "bvx"), ("vy", "bvy")):
+            self.stats[f"born.{c}"] = assert_close(f"born {c}", host(g.v[n]), b[c], POS_TOL, 1.0)
+        self.stats["born.w"] = assert_close("born w", host(g.v["bw"]), b["w"], W_TOL, 1e-12)
+        self.stats["update.status"] = g.status()
+        return cu
+
+    def moments(self):
+        g, p = self.g, self.p
+        g.moments()
+        torch.cuda.synchronize()
+        srt = g.state(sorted_=True)
+        start, end = u32(g.v["cell_start"]), u32(g.v["cell_end"])
+        m = oracle.moments(p.C, srt["w"], srt["vx"], srt["vy"], start, end,
+                           host(g.v["rho_p"]).astype(np.float64))
+        assert np.array_equal(host(g.v["mom_flag"]), m["flag"]), "moment flags"
+        for c in ("mean_x", "mean_y"):
+            self.stats[f"moments.{c}"] = assert_close(c, host(g.v[c]), m[c], MOM_TOL, 1.0)
+        scale_x = m["var_x"] + m["mean_x"] ** 2
+        scale_y = m["var_y"] + m["mean_y"] ** 2
+        scale_xy = np.sqrt(np.maximum(m["var_x"] * m["var_y"], 0)) + np.abs(m["mean_x"] * m["mean_y"])
+        for c, sc in (("var_x", scale_x), ("var_y", scale_y), ("cov_xy", scale_xy)):
+            d = np.abs(host(g.v[c]).astype(np.float64) - m[c])
+            err = float(np.max(d / np.maximum(sc, 1e-12))) if d.size else 0.0
+            assert err <= MOM_TOL, f"{c}: {err:.3e}"
+            self.stats[f"moments.{c}"] = err
+        return m
+
+    def resample(self):
+        g, p = self.g, self.p
+        k = g.cycle
+        pers = g.state(sorted_=True)
+        born = {c: host(g.v[n]) for c, n in (("x", "bx"), ("y", "by"), ("vx", "bvx"),
+                                             ("vy", "bvy"), ("w", "bw"))}
+        g.resample()
+        torch.cuda.synchronize()
+        ref, idx, W = oracle.resample(p, k, pers, born)
+        assert int(g.v["W_fixed"].item()) == W, "joint weight"
+        got = g.state()
+        for c in ("x", "y", "vx", "vy", "w"):
+            assert np.array_equal(got[c], ref[c].astype(np.float32)), f"resampled {c}"
+        assert g.cycle == k + 1 and int(g.v["cycle"].item()) == k + 1
+
+    def cycle(self, meas: dogm.Meas):
+        self.predict()
+        self.assign()
+        self.update(meas)
+        self.moments()
+        self.resample()
+        assert self.g.status() & dogm.ST_INTERNAL == 0, "internal consistency check failed"
+        return dict(self.stats)
+
+
+def device_meas(m: dict, device="cuda") -> dogm.Meas:
+    t = {k: (torch.as_tensor(np.ascontiguousarray(v, np.float32), device=device)
+             if v is not None else None) for k, v in m.items()
+         if k in ("m_occ", "m_free", "p_assoc", "mu_vx", "mu_vy", "var_v")}
+    return dogm.Meas(t["m_occ"], t["m_free"], t.get("p_assoc"), t.get("mu_vx"), t.get("mu_vy"),
+                     t.get("var_v"))
