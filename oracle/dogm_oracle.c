@@ -499,7 +499,8 @@ double or_resample_offset(const or_params* p, uint32_t cycle)
  * (multiples of 2^-40) through *W_fixed.  Every resampled particle gets weight W/nu.
  * With W == 0 the persistent set is kept as it is: idx[j] = j.
  *   F_i = sum_{i' <= i} q_i'      q_i = round(w_i 2^40)
- *   t_j = floor((j + U) W / nu)   (FP64)
+ *   d   = W / nu                  (the draw spacing, rounded once to FP64)
+ *   t_j = floor((j + U) d)        (FP64)
  *   idx_j = min { i : F_i > t_j } (last positive-weight index if none) */
 void or_resample_indices(int64_t nu, int64_t nb, const double* w_pers, const double* w_born,
                          double U, int64_t* idx, uint64_t* W_fixed)
@@ -521,10 +522,10 @@ void or_resample_indices(int64_t nu, int64_t nb, const double* w_pers, const dou
         free(F);
         return;
     }
-    double Wd = (double)acc;
+    double spacing = (double)acc / (double)nu;
     int64_t i = 0;
     for (int64_t j = 0; j < nu; ++j) {
-        double u = ((double)j + U) * Wd / (double)nu;
+        double u = ((double)j + U) * spacing;
         uint64_t t = (uint64_t)floor(u);
         while (i < N && F[i] <= t) ++i;
         idx[j] = i < N ? i : last_pos;

@@ -440,7 +440,7 @@ def test_resample_zero_total_keeps_state(orc):
 
 
 def test_resample_draw_lies_in_chosen_interval(orc):
-    """Each systematic draw u_j = (j + U) W / nu lies in the half-open CDF interval
+    """Each systematic draw u_j = (j + U) d, d = W / nu, lies in the half-open CDF interval
     [F_{i-1}, F_i) of the particle it selects (exact rationals).  Includes draws that hit a
     boundary exactly: those belong to the next particle."""
     # w = (1/4, 3/4), nu = 2, U = 1/2: u_0 = W/4 = F_0 exactly -> particle 1
@@ -453,7 +453,9 @@ def test_resample_draw_lies_in_chosen_interval(orc):
     assert list(idx) == [0, 1, 2, 3, 4, 5, 6, 7]
     rng = np.random.default_rng(17)
     for trial in range(40):
-        nu, nb = int(rng.integers(1, 40)), int(rng.integers(0, 10))
+        # nu a power of two: the spacing W / nu and every draw are exact in FP64, so the
+        # oracle's draws equal the exact rationals below
+        nu, nb = 2 ** int(rng.integers(0, 6)), int(rng.integers(0, 10))
         wp = rng.integers(0, 9, nu) * 2.0 ** -6
         wb = rng.integers(0, 9, nb) * 2.0 ** -6
         if wp.sum() + wb.sum() == 0:
