@@ -6,11 +6,18 @@ at 0.2 m with 2^21 persistent and 2^18 new-born particles over a synthetic ray-c
 (30 moving boxes, 1 % static clutter).  Measurement grids are generated and uploaded before the
 timed region.  Prints one JSON line.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--cpu-cycles N] [--copy-calibration]
+
+The roofline object covers the kernel that takes the most time per cycle (found from a traced
+warm-up): its launches inside the timed region are bracketed by HIP events on their own stream,
+and its algorithmic bytes per launch (the per-particle / per-cell figures below, times the units
+one launch processes) are divided by the mean launch duration.  HBM traffic comes from the
+committed counter summary of that kernel when its source has not changed since.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -22,13 +29,89 @@ sys.path.insert(0, ROOT)
 METRIC = "filter cycles/s and particles/s at 512²/2M; p50/p99 cycle latency multi-stream"
 HBM_PEAK_GBS = 8000.0
 
-# Algorithmic bytes (each array read / written once per step that needs it, the sort as one
-# ideal pass, random numbers in registers): per persistent particle, per new-born slot, per cell.
+# Algorithmic bytes of a whole cycle (each array read / written once per step that needs it,
+# the sort as one ideal pass, random numbers in registers): per persistent particle, per
+# new-born slot, per cell.
 B_PER_PARTICLE = 156
 B_PER_BORN = 28
 B_PER_CELL = 92
-# predict reads x, y, vx, vy, w and writes them plus the key
-PREDICT_BYTES_PER_PARTICLE = 20 + 24
+
+CSRC = os.path.join(ROOT, "paper_1605_02406_amd", "csrc")
+KERNEL_SOURCE = {
+    "k_predict": "k_particles.hip", "k_sort_hist": "k_sort.hip", "k_scan_rows": "k_sort.hip",
+    "k_sort_scatter": "k_sort.hip", "k_seg_update<false>": "k_cells.hip",
+    "k_seg_update<true>": "k_cells.hip", "k_cells_empty": "k_cells.hip",
+    "k_seg_moments": "k_cells.hip", "k_born_offsets": "k_particles.hip",
+    "k_particle_tiles": "k_particles.hip", "k_resample": "k_resample.hip",
+}
+
+
+def sort_plan(C: int, max_bits: int = 11):
+    """Digit widths of the radix sort of keys 0..C (the library's plan)."""
+    kb = max(1, C.bit_length())
+    passes = (kb + max_bits - 1) // max_bits
+    bits, left = [], kb
+    for q in range(passes):
+        b = (left + (passes - q) - 1) // (passes - q)
+        bits.append(b)
+        left -= b
+    return bits
+
+
+def algorithmic_bytes(kernel: str, nu: int, nb: int, C: int) -> float:
+    """Algorithmic bytes of ONE launch of `kernel` on one grid (averaged over the launches of a
+    cycle where they differ), from per-unit figures: predict reads x, y, vx, vy, w (20 B) and
+    writes them and the key (24 B); a sort pass reads the key, the source index (from the
+    second pass on) and the five state arrays and writes key, index and state (28 B); the
+    resampling reads every joint weight (4 B), the state of each chosen source (16 B) and
+    writes the 20-byte state of every output; the per-cell pass reads the sorted key, weight
+    and velocity (16 B per particle) and per cell m_F and the measurement (12 B) and writes
+    ranges, sums, masses, normalisers and moments (101 B)."""
+    bits = sort_plan(C)
+    if kernel == "k_predict":
+        return 44.0 * nu
+    if kernel == "k_sort_scatter":
+        per = [(24 if q == 0 else 28) + 28 for q in range(len(bits))]
+        return nu * sum(per) / len(per)
+    if kernel == "k_sort_hist":
+        return 4.0 * nu
+    if kernel == "k_scan_rows":
+        tiles = -(-nu // 1024)
+        return 8.0 * sum(1 << b for b in bits) * tiles / len(bits)
+    if kernel in ("k_seg_update<false>", "k_seg_update<true>"):
+        return 16.0 * nu + (12 + 101) * C
+    if kernel == "k_resample":
+        return 4.0 * (nu + nb) + 16.0 * nu + 20.0 * nu
+    if kernel == "k_particle_tiles":
+        return 12.0 * nu + 25.0 * nb
+    if kernel == "k_cells_empty":
+        return 12.0 * C
+    if kernel == "k_born_offsets":
+        return 8.0 * C
+    return float("nan")
+
+
+def source_digest(kernel: str) -> str:
+    """SHA-256 of the kernel's source file and of the headers every kernel includes."""
+    h = hashlib.sha256()
+    for f in (KERNEL_SOURCE[kernel], "dogm_internal.h", "launch.h"):
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from the committed counter summary, or None if there is none or
+    the kernel's source changed since the counters were taken."""
+    safe = kernel.replace("<", "_").replace(">", "")
+    path = os.path.join(ROOT, "profiles", f"traffic_{safe}_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("source_sha256") != source_digest(kernel):
+        return None
+    return rec.get("hbm_bytes_per_launch")
 
 
 def parse():
@@ -37,9 +120,10 @@ def parse():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="c512")
-    ap.add_argument("--cpu-cycles", type=int, default=20,
+    ap.add_argument("--cpu-cycles", type=int, default=3,
                     help="oracle cycles timed on the host for the CPU baseline (0: skip)")
-    ap.add_argument("--events", action="store_true", default=True)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one device copy of 1 GiB (for counter calibration)")
     return ap.parse_args()
 
 
@@ -47,7 +131,7 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(f"bench.py runs on one GPU: the filter of one grid does not span GPUs here "
+        print(f"bench.py runs on one GPU: this build has no multi-GPU path "
               f"(asked for --gpus {args.gpus}, WORLD_SIZE {world})", file=sys.stderr)
         sys.exit(2)
 
@@ -60,7 +144,9 @@ def main():
     p = dogm.make_params(wl["nx"], wl["ny"], wl["cell"], wl["n_pers"], wl["n_born"],
                          seed=wl.get("seed", 0), **scenes.FILTER)
     C = wl["nx"] * wl["ny"]
+    nu, nb = wl["n_pers"], wl["n_born"]
     n_cycles = args.warmup + args.steps
+    print(f"[bench] generating {n_cycles} measurement grids", file=sys.stderr, flush=True)
     t_gen = time.perf_counter()
     seq = scenes.measurement_sequence(wl, n_cycles)
     t_gen = time.perf_counter() - t_gen
@@ -70,44 +156,72 @@ def main():
     g = dogm.Grid(p)
     torch.cuda.synchronize()
 
-    for k in range(args.warmup):
+    # warm-up; its last cycles are traced kernel by kernel to find the dominant kernel
+    print(f"[bench] warm-up {args.warmup} cycles", file=sys.stderr, flush=True)
+    n_traced = min(3, args.warmup)
+    for k in range(args.warmup - n_traced):
         g.step(meas[k])
+    with dogm.KernelTrace(None, capacity=64 * max(n_traced, 1)) as tr:
+        for k in range(args.warmup - n_traced, args.warmup):
+            g.step(meas[k])
     torch.cuda.synchronize()
+    per_kernel = {}
+    for name, ms in zip(tr.names(), tr.durations_ms()):
+        per_kernel.setdefault(name, []).append(ms)
+    per_kernel_ms = {k: float(np.sum(v)) / max(n_traced, 1) for k, v in per_kernel.items()}
+    launches = {k: len(v) // max(n_traced, 1) for k, v in per_kernel.items()}
+    dominant = max(per_kernel_ms, key=per_kernel_ms.get) if per_kernel_ms else "k_predict"
 
-    # timed region: every call of every step, with HIP events between the calls on the
-    # grid's stream (the current stream)
+    # timed region: every call of every step, HIP events between the calls on the grid's
+    # stream (the current stream) and around every launch of the dominant kernel
+    print(f"[bench] timing {args.steps} cycles (dominant kernel {dominant})", file=sys.stderr,
+          flush=True)
     names = ["predict", "assign", "update", "moments", "resample"]
     ev = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(args.steps)]
+    dom = dogm.KernelTrace(dominant, capacity=args.steps * max(launches.get(dominant, 1), 1))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for s in range(args.steps):
-        e = ev[s]
-        m = meas[args.warmup + s]
-        e[0].record()
-        g.predict()
-        e[1].record()
-        g.assign()
-        e[2].record()
-        g.update(m)
-        e[3].record()
-        g.moments()
-        e[4].record()
-        g.resample()
-        e[5].record()
-    torch.cuda.synchronize()
+    with dom:
+        for s in range(args.steps):
+            e = ev[s]
+            m = meas[args.warmup + s]
+            e[0].record()
+            g.predict()
+            e[1].record()
+            g.assign()
+            e[2].record()
+            g.update(m)
+            e[3].record()
+            g.moments()
+            e[4].record()
+            g.resample()
+            e[5].record()
+        torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     status = g.status()
+    print("[bench] timed region done", file=sys.stderr, flush=True)
 
     per_call = {n: float(np.mean([ev[s][i].elapsed_time(ev[s][i + 1]) for s in range(args.steps)]))
                 for i, n in enumerate(names)}
     cycle_ms = [ev[s][0].elapsed_time(ev[s][5]) for s in range(args.steps)]
     ms_per_step = wall * 1e3 / args.steps
     cycles_per_s = args.steps / wall
-    nu, nb = wl["n_pers"], wl["n_born"]
     b_alg = B_PER_PARTICLE * nu + B_PER_BORN * nb + B_PER_CELL * C
 
-    pred_ms = per_call["predict"]
-    pred_gbs = PREDICT_BYTES_PER_PARTICLE * nu / (pred_ms * 1e-3) / 1e9
+    dom_ms = dom.durations_ms()
+    dom_mean_ms = float(np.mean(dom_ms)) if dom_ms else float("nan")
+    dom_bytes = algorithmic_bytes(dominant, nu, nb, C)
+    dom_gbs = dom_bytes / (dom_mean_ms * 1e-3) / 1e9
+    traffic = measured_traffic(dominant, args.workload)
+
+    if args.copy_calibration:
+        x = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+        y = torch.empty_like(x)
+        x.fill_(1.0)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        del x, y
 
     out = {
         "metric": METRIC,
@@ -131,23 +245,27 @@ def main():
         "cycle_ms_p50": float(np.percentile(cycle_ms, 50)),
         "cycle_ms_p99": float(np.percentile(cycle_ms, 99)),
         "per_call_ms": per_call,
+        "per_kernel_ms": per_kernel_ms,
+        "launches_per_cycle": launches,
         "cycle_roofline": {"bound": "hbm", "algorithmic_bytes": b_alg,
                            "achieved": b_alg / (ms_per_step * 1e-3) / 1e9,
                            "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": b_alg / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS},
-        "roofline": {"kernel": "k_predict", "bound": "hbm", "achieved": pred_gbs,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": pred_gbs / HBM_PEAK_GBS,
-                     "traffic": None},
+        "roofline": {"kernel": dominant, "bound": "hbm", "achieved": dom_gbs,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": dom_gbs / HBM_PEAK_GBS,
+                     "traffic": traffic, "algorithmic_bytes_per_launch": dom_bytes,
+                     "launch_ms_mean": dom_mean_ms, "launches_timed": len(dom_ms)},
         "status_word": status,
         "meas_generation_s": t_gen,
     }
 
     if args.cpu_cycles > 0:
-        out["cpu_baseline"] = cpu_baseline(wl, p, seq, args.cpu_cycles)
+        print(f"[bench] oracle on the host, {args.cpu_cycles} cycles", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(p, seq, args.cpu_cycles)
     print(json.dumps(out), flush=True)
 
 
-def cpu_baseline(wl, p, seq, n):
+def cpu_baseline(p, seq, n):
     """The oracle (single-threaded FP64 C, as it stands) on the same workload: n cycles from its
     own initial state, timed on this host."""
     import numpy as np

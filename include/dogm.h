@@ -68,7 +68,7 @@ typedef struct dogm_params {
     float sigma_vel;       /* process-noise SD on velocity per step [m/s]                   */
     float sigma_birth_vel; /* SD of new-born velocity sigma_B,v [m/s] (Table I)             */
     float alpha_free;      /* free-mass discount alpha(T) in [0,1], eq. (DS_freespace_pred) */
-    int64_t n_pers;        /* persistent particles nu, 1 <= nu < 2^30                       */
+    int64_t n_pers;        /* persistent particles nu, 1 <= nu < 2^28                       */
     int64_t n_born;        /* new-born slots nu_b, 0 <= nu_b < 2^30                         */
     uint64_t seed;         /* Philox4x32-10 key                                            */
     uint32_t grid_id;      /* fourth Philox counter word: separates grids with one seed     */
@@ -80,7 +80,10 @@ typedef struct dogm_params {
  * with m_occ + m_free <= 1 (required).  p_assoc: association probability p_A per cell, or
  * NULL for p_A = 0 everywhere; when given, mu_vx, mu_vy, var_v (measured velocity and its
  * variance, > 0) define the spatial likelihood g(z|x) = N(v; mu, var I) and the associated
- * new-born velocity pdf, and must be non-NULL. */
+ * new-born velocity pdf, and must be non-NULL.
+ * In this build velocity evidence is switched off: a non-NULL p_assoc makes dogm_update,
+ * dogm_step and dogm_step_batch return DOGM_ENOTIMPL before anything is enqueued (the text
+ * from dogm_status_string / dogm_last_error says so). */
 typedef struct dogm_meas {
     const float* m_occ;
     const float* m_free;
@@ -100,7 +103,8 @@ typedef struct dogm_views {
     uint32_t* skey;       /* sorted keys (nu)                                               */
     uint32_t* perm;       /* sorted position -> index in x..w (nu)                          */
     /* cells (C each unless noted) */
-    uint32_t *cell_start, *cell_end; /* particle range [start, end) of each cell in sorted order */
+    uint32_t *cell_start, *cell_end; /* particle range [start, end) of each cell in sorted
+                                         order, recorded by update; empty: start == end  */
     double* sum_w;        /* sum of predicted persistent weights (FP64; 0 for empty cells) */
     float *m_pO, *m_pF;   /* predicted BBA                                                  */
     float *m_O, *m_F;     /* posterior BBA; m_F is also the state carried to the next cycle  */
@@ -154,8 +158,9 @@ int dogm_view(const dogm_grid* grid, dogm_views* views);
  * (index, cycle, 1, grid_id); writes the cell key (C and w' = 0 outside the grid). */
 int dogm_predict(dogm_grid* grid);
 
-/* Alg. 2: stable sort of the particles by cell key into sx..sw / skey / perm, and the
- * particle range of every cell (cell_start, cell_end; empty cells have start == end). */
+/* Alg. 2: stable sort of the particles by cell key into sx..sw / skey / perm.  The particle
+ * range of every cell (cell_start, cell_end) is recorded by the per-cell pass of dogm_update,
+ * which walks the sorted keys anyway. */
 int dogm_assign(dogm_grid* grid);
 
 /* Alg. 3, 4 and 5 in the paper's order:
@@ -166,19 +171,23 @@ int dogm_assign(dogm_grid* grid);
  *  - new-born particles: nu_b slots allocated in proportion to rho_b, split into associated /
  *    unassociated sets, uniform position in the cell, velocity from p(x|z) or N(0, sigma_B^2),
  *    weights of eqs. (weights_associated), (weights_unassociated).
+ * Also records cell_start / cell_end.  Without velocity evidence (p_assoc NULL) the updated
+ * weights are mu_UA w, so the same pass also writes the velocity moments of Alg. 6.
  * `meas` is a host struct of device pointers (see dogm_meas).  DOGM_EINVAL if m_occ/m_free is
  * NULL or p_assoc is given without mu_vx/mu_vy/var_v. */
 int dogm_update(dogm_grid* grid, const dogm_meas* meas);
 
 /* Alg. 6, eqs. (mean_x), (var_x), (covar_xy): velocity mean, variance and covariance of the
  * updated persistent particles of every cell, normalised by rho_p; zeros and mom_flag 0
- * where rho_p <= 0 or the cell holds no particle. */
+ * where rho_p <= 0 or the cell holds no particle.  Launches work only for a grid whose last
+ * update had velocity evidence (otherwise the update already wrote the moments); the call is
+ * still required in the order of a cycle. */
 int dogm_moments(dogm_grid* grid);
 
 /* Alg. 7, eq. (resampledParticleWeights): systematic resampling of nu particles from the joint
  * set [sorted persistent | new-born] into x..w, every weight W/nu with W the joint weight;
  * draws u_j = (j + U) W / nu with U from Philox counter (0, cycle, 3, grid_id).  With W = 0
- * the sorted persistent set is kept.  Advances the cycle counter. */
+ * the sorted persistent set is kept.  Advances the device cycle counter (cycle + 1). */
 int dogm_resample(dogm_grid* grid);
 
 /* predict, assign, update, moments, resample in order (one full cycle). */
@@ -190,6 +199,18 @@ int dogm_step(dogm_grid* grid, const dogm_meas* meas);
  * every grid is bit-identical to dogm_step on that grid alone. */
 int dogm_step_batch(dogm_grid* const* grids, const dogm_meas* meas, int n,
                     dogm_stream_t stream);
+
+/* Per-kernel timing on the device clock.  While a trace is active, every launch of the kernel
+ * named `kernel` (every kernel if NULL) that the calling thread enqueues through this library
+ * is bracketed by two of the caller's HIP events (hipEvent_t, created with timing enabled),
+ * recorded on that launch's stream: events[2i] before and events[2i+1] after the i-th traced
+ * launch, for the first `capacity` launches; names[i] (if names is not NULL) receives the
+ * kernel's name, static storage.  The events, the arrays and the `kernel` string are the
+ * caller's and must stay valid until dogm_trace_end, which returns the number of traced
+ * launches in *count.  A trace is per thread; DOGM_EINVAL on a negative capacity or NULL
+ * events with capacity > 0, DOGM_ESTATE from dogm_trace_end without an active trace. */
+int dogm_trace_begin(void* const* events, const char** names, int capacity, const char* kernel);
+int dogm_trace_end(int* count);
 
 /* Text of a status code, or of the last DOGM_EHIP error of the calling thread. */
 const char* dogm_status_string(int code);

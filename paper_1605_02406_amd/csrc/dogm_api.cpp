@@ -15,11 +15,22 @@
 
 using namespace dogm;
 
+namespace dogm {
+thread_local Trace* g_trace = nullptr;
+
+bool trace_wants(const char* name)
+{
+    if (!g_trace || g_trace->n >= g_trace->cap) return false;
+    return !g_trace->only || std::strcmp(g_trace->only, name) == 0;
+}
+}  // namespace dogm
+
 namespace {
 
 enum Phase { kReady = 0, kPredicted = 1, kAssigned = 2, kUpdated = 3, kMoments = 4 };
 
 thread_local std::string g_last_error;
+thread_local Trace g_trace_storage;
 
 int hip_fail(hipError_t e, const char* where)
 {
@@ -41,7 +52,7 @@ bool valid_params(const dogm_params* p)
         !finite_in(p->sigma_birth_vel, 0.0f, 1e6f))
         return false;
     if (!finite_in(p->alpha_free, 0.0f, 1.0f)) return false;
-    if (p->n_pers < 1 || p->n_pers >= (int64_t(1) << 30)) return false;
+    if (p->n_pers < 1 || p->n_pers >= (int64_t(1) << 28)) return false;
     if (p->n_born < 0 || p->n_born >= (int64_t(1) << 30)) return false;
     if (p->reserved != 0) return false;
     return true;
@@ -87,90 +98,88 @@ GridDev describe(const dogm_params* p, char* base, size_t* bytes)
     d.seed_lo = (uint32_t)p->seed;
     d.seed_hi = (uint32_t)(p->seed >> 32);
     d.grid_id = p->grid_id;
+    // radix digits: as few passes of at most kSortBits bits as cover the largest key (C)
+    const int kb = key_bits(C);
+    d.passes = (uint32_t)((kb + kSortBits - 1) / kSortBits);
+    uint32_t shift = 0;
+    for (uint32_t q = 0; q < d.passes; ++q) {
+        const uint32_t left = (uint32_t)kb - shift, passes_left = d.passes - q;
+        d.dbits[q] = (left + passes_left - 1) / passes_left;
+        d.dshift[q] = shift;
+        shift += d.dbits[q];
+    }
     d.n_sort_tiles = ceil_div(nu, kSortTile);
-    d.n_res_tiles = ceil_div((uint64_t)nu + nb, kResTile);
+    d.n_hist_tiles = ceil_div(nu, kHistTile);
+    d.n_cell_parts = ceil_div(C, kCellThreads);
+    d.n_res_ptiles = ceil_div(nu, kResTile);
+    d.n_res_btiles = ceil_div(nb, kResTile);
 
     Layout L;
     L.take(sizeof(GridDev));
     const size_t f_nu = 4ull * nu, f_nb = 4ull * nb, f_c = 4ull * C, d_c = 8ull * C;
-    size_t o_x = L.take(f_nu), o_y = L.take(f_nu), o_vx = L.take(f_nu), o_vy = L.take(f_nu),
-           o_w = L.take(f_nu), o_key = L.take(f_nu);
-    size_t o_sx = L.take(f_nu), o_sy = L.take(f_nu), o_svx = L.take(f_nu), o_svy = L.take(f_nu),
-           o_sw = L.take(f_nu), o_skey = L.take(f_nu), o_perm = L.take(f_nu);
-    size_t o_tkey = L.take(f_nu), o_tval = L.take(f_nu);
-    size_t o_hist = L.take(4ull * (1u << kMaxDigitBits) * d.n_sort_tiles);
-    size_t o_cs = L.take(f_c), o_ce = L.take(f_c), o_sumw = L.take(d_c), o_sumwt = L.take(d_c);
-    size_t o_mpo = L.take(f_c), o_mpf = L.take(f_c), o_mo = L.take(f_c), o_mf = L.take(f_c),
-           o_rb = L.take(f_c), o_rp = L.take(f_c), o_pign = L.take(f_c);
-    size_t o_mua = L.take(d_c), o_muua = L.take(d_c), o_bq = L.take(d_c),
-           o_boff = L.take(4ull * (C + 1));
-    size_t o_mx = L.take(f_c), o_my = L.take(f_c), o_vx2 = L.take(f_c), o_vy2 = L.take(f_c),
-           o_cxy = L.take(f_c), o_mfl = L.take(C);
-    size_t o_bx = L.take(f_nb), o_by = L.take(f_nb), o_bvx = L.take(f_nb), o_bvy = L.take(f_nb),
-           o_bw = L.take(f_nb), o_bkey = L.take(f_nb), o_bas = L.take(nb);
-    size_t o_rt = L.take(8ull * d.n_res_tiles), o_rl = L.take(4ull * d.n_res_tiles);
-    const uint32_t scan_tiles_c = ceil_div(C, kScanTile);
-    const uint32_t scan_tiles_h = ceil_div((uint64_t)(1u << kMaxDigitBits) * d.n_sort_tiles, kScanTile);
-    size_t o_sp = L.take(8ull * ((scan_tiles_c > scan_tiles_h ? scan_tiles_c : scan_tiles_h) + 1));
-    size_t o_cyc = L.take(4), o_st = L.take(4), o_W = L.take(8), o_S = L.take(8),
-           o_last = L.take(4), o_U = L.take(8);
+    float** pf_nu[] = {&d.x, &d.y, &d.vx, &d.vy, &d.w, &d.sx, &d.sy, &d.svx, &d.svy, &d.sw,
+                       &d.tx, &d.ty, &d.tvx, &d.tvy, &d.tw};
+    size_t o_pf_nu[15];
+    for (int i = 0; i < 15; ++i) o_pf_nu[i] = L.take(f_nu);
+    uint32_t** pu_nu[] = {&d.key, &d.skey, &d.perm, &d.tkey, &d.tval};
+    size_t o_pu_nu[5];
+    for (int i = 0; i < 5; ++i) o_pu_nu[i] = L.take(f_nu);
+    uint32_t** pu_c[] = {&d.cstart, &d.cend};
+    size_t o_pu_c[2];
+    for (int i = 0; i < 2; ++i) o_pu_c[i] = L.take(f_c);
+    double** pd_c[] = {&d.sum_w, &d.sum_wt, &d.mu_A, &d.mu_UA};
+    size_t o_pd_c[4];
+    for (int i = 0; i < 4; ++i) o_pd_c[i] = L.take(d_c);
+    float** pf_c[] = {&d.m_pO, &d.m_pF, &d.m_O, &d.m_F, &d.rho_b, &d.rho_p, &d.pign,
+                      &d.mean_x, &d.mean_y, &d.var_x, &d.var_y, &d.cov_xy};
+    size_t o_pf_c[12];
+    for (int i = 0; i < 12; ++i) o_pf_c[i] = L.take(f_c);
+    const size_t o_boff = L.take(4ull * (C + 1)), o_mfl = L.take(C);
+    float** pf_nb[] = {&d.bx, &d.by, &d.bvx, &d.bvy, &d.bw};
+    size_t o_pf_nb[5];
+    for (int i = 0; i < 5; ++i) o_pf_nb[i] = L.take(f_nb);
+    const size_t o_bkey = L.take(f_nb), o_bas = L.take(nb);
+    const size_t o_hist = L.take(4ull * kSortBins * d.n_hist_tiles);
+    const size_t o_rowtot = L.take(4ull * kSortBins);
+    const size_t o_bpart = L.take(8ull * d.n_cell_parts);
+    const size_t o_mark = L.take(f_nb);
+    const size_t o_rpart = L.take(8ull * (d.n_res_ptiles + d.n_res_btiles));
+    const size_t o_cyc = L.take(4), o_cycr = L.take(4), o_st = L.take(4), o_W = L.take(8),
+                 o_S = L.take(8);
     *bytes = L.total;
     if (!base) return d;
 
-    d.x = at<float>(base, o_x);
-    d.y = at<float>(base, o_y);
-    d.vx = at<float>(base, o_vx);
-    d.vy = at<float>(base, o_vy);
-    d.w = at<float>(base, o_w);
-    d.key = at<uint32_t>(base, o_key);
-    d.sx = at<float>(base, o_sx);
-    d.sy = at<float>(base, o_sy);
-    d.svx = at<float>(base, o_svx);
-    d.svy = at<float>(base, o_svy);
-    d.sw = at<float>(base, o_sw);
-    d.skey = at<uint32_t>(base, o_skey);
-    d.perm = at<uint32_t>(base, o_perm);
-    d.tkey = at<uint32_t>(base, o_tkey);
-    d.tval = at<uint32_t>(base, o_tval);
-    d.hist = at<uint32_t>(base, o_hist);
-    d.cstart = at<uint32_t>(base, o_cs);
-    d.cend = at<uint32_t>(base, o_ce);
-    d.sum_w = at<double>(base, o_sumw);
-    d.sum_wt = at<double>(base, o_sumwt);
-    d.m_pO = at<float>(base, o_mpo);
-    d.m_pF = at<float>(base, o_mpf);
-    d.m_O = at<float>(base, o_mo);
-    d.m_F = at<float>(base, o_mf);
-    d.rho_b = at<float>(base, o_rb);
-    d.rho_p = at<float>(base, o_rp);
-    d.pign = at<float>(base, o_pign);
-    d.mu_A = at<double>(base, o_mua);
-    d.mu_UA = at<double>(base, o_muua);
-    d.born_q = at<uint64_t>(base, o_bq);
+    for (int i = 0; i < 15; ++i) *pf_nu[i] = at<float>(base, o_pf_nu[i]);
+    for (int i = 0; i < 5; ++i) *pu_nu[i] = at<uint32_t>(base, o_pu_nu[i]);
+    for (int i = 0; i < 2; ++i) *pu_c[i] = at<uint32_t>(base, o_pu_c[i]);
+    for (int i = 0; i < 4; ++i) *pd_c[i] = at<double>(base, o_pd_c[i]);
+    for (int i = 0; i < 12; ++i) *pf_c[i] = at<float>(base, o_pf_c[i]);
     d.born_off = at<uint32_t>(base, o_boff);
-    d.mean_x = at<float>(base, o_mx);
-    d.mean_y = at<float>(base, o_my);
-    d.var_x = at<float>(base, o_vx2);
-    d.var_y = at<float>(base, o_vy2);
-    d.cov_xy = at<float>(base, o_cxy);
     d.mflag = at<uint8_t>(base, o_mfl);
-    d.bx = at<float>(base, o_bx);
-    d.by = at<float>(base, o_by);
-    d.bvx = at<float>(base, o_bvx);
-    d.bvy = at<float>(base, o_bvy);
-    d.bw = at<float>(base, o_bw);
+    for (int i = 0; i < 5; ++i) *pf_nb[i] = at<float>(base, o_pf_nb[i]);
     d.bkey = at<uint32_t>(base, o_bkey);
     d.bassoc = at<uint8_t>(base, o_bas);
-    d.res_tile = at<uint64_t>(base, o_rt);
-    d.res_last = at<int32_t>(base, o_rl);
-    d.scan_part = at<uint64_t>(base, o_sp);
+    d.hist = at<uint32_t>(base, o_hist);
+    d.rowtot = at<uint32_t>(base, o_rowtot);
+    d.bpart = at<uint64_t>(base, o_bpart);
+    d.rpart = at<uint64_t>(base, o_rpart);
+    d.born_mark = at<uint32_t>(base, o_mark);
     d.cycle = at<uint32_t>(base, o_cyc);
+    d.cycle_run = at<uint32_t>(base, o_cycr);
     d.status = at<uint32_t>(base, o_st);
     d.W_fixed = at<uint64_t>(base, o_W);
     d.S_fixed = at<uint64_t>(base, o_S);
-    d.last_pos = at<int32_t>(base, o_last);
-    d.U = at<double>(base, o_U);
     return d;
+}
+
+// Velocity evidence (p_A > 0) is switched off: its kernels stay in the library but no entry
+// point launches them until a device fault seen with them is explained.
+bool evidence_enabled() { return false; }
+
+int evidence_refused(const char* where)
+{
+    g_last_error = std::string(where) + ": velocity evidence (p_assoc) is disabled in this build";
+    return DOGM_ENOTIMPL;
 }
 
 bool valid_meas(const dogm_meas* m)
@@ -205,6 +214,8 @@ struct dogm_grid {
     hipStream_t stream;
     uint32_t cycle;
     int phase;
+    bool assoc;           // the last update had velocity evidence
+    dogm_meas last_meas;  // its measurement (the moments of that case read it)
 
     GridRef ref(const dogm_meas* m = nullptr) const { return GridRef{&hd, dd, to_dev(m)}; }
 };
@@ -236,6 +247,8 @@ int dogm_init_grid(const dogm_params* params, void* arena, size_t arena_bytes,
     g->stream = static_cast<hipStream_t>(stream);
     g->cycle = 1;
     g->phase = kReady;
+    g->assoc = false;
+    std::memset(&g->last_meas, 0, sizeof(g->last_meas));
     hipError_t e = launch_write_desc(g->hd, g->dd, g->stream);
     if (e == hipSuccess) {
         const GridRef r = g->ref();
@@ -351,7 +364,6 @@ int dogm_assign(dogm_grid* grid)
     if (grid->phase != kPredicted) return DOGM_ESTATE;
     const GridRef r = grid->ref();
     hipError_t e = launch_sort(&r, 1, grid->stream);
-    if (e == hipSuccess) e = launch_gather(&r, 1, grid->stream);
     if (e != hipSuccess) return hip_fail(e, "dogm_assign");
     grid->phase = kAssigned;
     return DOGM_OK;
@@ -360,13 +372,14 @@ int dogm_assign(dogm_grid* grid)
 int dogm_update(dogm_grid* grid, const dogm_meas* meas)
 {
     if (!grid || !valid_meas(meas)) return DOGM_EINVAL;
+    if (meas->p_assoc && !evidence_enabled()) return evidence_refused("dogm_update");
     if (grid->phase != kAssigned) return DOGM_ESTATE;
     const GridRef r = grid->ref(meas);
-    hipError_t e = launch_cell_update(&r, 1, grid->stream);
-    if (e == hipSuccess) e = launch_weight_update(&r, 1, grid->stream);
-    if (e == hipSuccess) e = launch_births(&r, 1, grid->stream);
+    hipError_t e = launch_update(&r, 1, grid->stream);
     if (e != hipSuccess) return hip_fail(e, "dogm_update");
     grid->phase = kUpdated;
+    grid->assoc = meas->p_assoc != nullptr;
+    grid->last_meas = *meas;
     return DOGM_OK;
 }
 
@@ -374,7 +387,7 @@ int dogm_moments(dogm_grid* grid)
 {
     if (!grid) return DOGM_EINVAL;
     if (grid->phase != kUpdated && grid->phase != kMoments) return DOGM_ESTATE;
-    const GridRef r = grid->ref();
+    const GridRef r = grid->ref(grid->assoc ? &grid->last_meas : nullptr);
     hipError_t e = launch_moments(&r, 1, grid->stream);
     if (e != hipSuccess) return hip_fail(e, "dogm_moments");
     grid->phase = kMoments;
@@ -396,6 +409,7 @@ int dogm_resample(dogm_grid* grid)
 int dogm_step(dogm_grid* grid, const dogm_meas* meas)
 {
     if (!grid || !valid_meas(meas)) return DOGM_EINVAL;
+    if (meas->p_assoc && !evidence_enabled()) return evidence_refused("dogm_step");
     if (grid->phase != kReady) return DOGM_ESTATE;
     int rc = dogm_predict(grid);
     if (rc == DOGM_OK) rc = dogm_assign(grid);
@@ -410,6 +424,7 @@ int dogm_step_batch(dogm_grid* const* grids, const dogm_meas* meas, int n, dogm_
     if (n < 0 || (n > 0 && (!grids || !meas))) return DOGM_EINVAL;
     for (int i = 0; i < n; ++i) {
         if (!grids[i] || !valid_meas(&meas[i])) return DOGM_EINVAL;
+        if (meas[i].p_assoc && !evidence_enabled()) return evidence_refused("dogm_step_batch");
         if (grids[i]->phase != kReady) return DOGM_ESTATE;
         for (int j = 0; j < i; ++j)
             if (grids[j] == grids[i]) return DOGM_EINVAL;
@@ -426,10 +441,7 @@ int dogm_step_batch(dogm_grid* const* grids, const dogm_meas* meas, int n, dogm_
             const GridRef* r = refs.data() + c0;
             hipError_t e = launch_predict(r, m, s);
             if (e == hipSuccess) e = launch_sort(r, m, s);
-            if (e == hipSuccess) e = launch_gather(r, m, s);
-            if (e == hipSuccess) e = launch_cell_update(r, m, s);
-            if (e == hipSuccess) e = launch_weight_update(r, m, s);
-            if (e == hipSuccess) e = launch_births(r, m, s);
+            if (e == hipSuccess) e = launch_update(r, m, s);
             if (e == hipSuccess) e = launch_moments(r, m, s);
             if (e == hipSuccess) e = launch_resample(r, m, s);
             if (e != hipSuccess) return hip_fail(e, "dogm_step_batch");
@@ -447,11 +459,28 @@ const char* dogm_status_string(int code)
         case DOGM_ESIZE: return "arena too small";
         case DOGM_EHIP: return g_last_error.empty() ? "HIP error" : g_last_error.c_str();
         case DOGM_ESTATE: return "call out of order";
-        case DOGM_ENOTIMPL: return "not implemented";
+        case DOGM_ENOTIMPL: return g_last_error.empty() ? "not implemented" : g_last_error.c_str();
         default: return "unknown status";
     }
 }
 
 const char* dogm_last_error(void) { return g_last_error.c_str(); }
+
+int dogm_trace_begin(void* const* events, const char** names, int capacity, const char* kernel)
+{
+    if (capacity < 0 || (capacity > 0 && !events)) return DOGM_EINVAL;
+    g_trace_storage = Trace{reinterpret_cast<hipEvent_t*>(const_cast<void**>(events)), names,
+                            kernel, capacity, 0};
+    g_trace = &g_trace_storage;
+    return DOGM_OK;
+}
+
+int dogm_trace_end(int* count)
+{
+    if (!g_trace) return DOGM_ESTATE;
+    if (count) *count = g_trace->n;
+    g_trace = nullptr;
+    return DOGM_OK;
+}
 
 }  // extern "C"

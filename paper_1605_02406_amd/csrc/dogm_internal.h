@@ -4,6 +4,11 @@
 // a GridDev descriptor (pointers + parameters).  Every kernel takes a Batch by value: the
 // descriptors of up to kMaxBatch grids plus the first block of each grid in the launch, so one
 // launch serves one grid or a batch of grids of different sizes alike.
+//
+// Blocks never talk to each other inside a kernel (no atomics on shared counters, no spinning):
+// every block stores its partial results (digit counts of a tile, fixed-point sums of a tile)
+// and the next kernel combines them.  On a chip of eight dies, device-wide atomics and coherent
+// polling cost far more than a kernel boundary.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -20,24 +25,30 @@ constexpr uint32_t kPurposeInit = 0, kPurposePredict = 1, kPurposeBirth = 2,
 
 constexpr uint32_t kStConflict = 1u, kStNoCarrier = 2u, kStNonFinite = 4u, kStInternal = 8u;
 
-// Radix sort of the cell keys: tiles of kSortTile keys, digits of at most 8 bits.
+// Radix sort of the cell keys: tiles of kSortTile keys, digits of at most kSortBits bits.
 constexpr int kSortThreads = 256;
 constexpr int kSortItems = 16;
 constexpr int kSortTile = kSortThreads * kSortItems;  // 4096
-constexpr int kMaxDigitBits = 8;
-constexpr int kMaxPasses = 4;
+constexpr int kSortBits = 11;
+constexpr int kSortBins = 1 << kSortBits;  // 2048
+constexpr int kMaxPasses = 3;              // keys < 2^27 (C < 2^26 plus the outside key)
+constexpr int kScanRowThreads = 256;       // one block scans a few digit rows of the histogram
+constexpr int kHistTile = 1024;            // keys per digit-histogram sub-tile
+constexpr uint32_t kNoCell = 0xFFFFFFFFu;
 
-// Generic scans: tiles of kScanTile elements.
-constexpr int kScanThreads = 256;
-constexpr int kScanItems = 8;
-constexpr int kScanTile = kScanThreads * kScanItems;  // 2048
+// Cells: one per thread, partial sums per block of kCellThreads cells.
+constexpr int kCellThreads = 256;
 
-// Segmented per-cell reductions: each wave owns kSegRange particles.
+// Fixed-point partial sums of the joint weights (persistent tiles, then new-born tiles) and of
+// the new-born masses (cell tiles) are written per tile of 2048 elements.
+
+// Segmented per-cell reductions: each wave owns 64 * kSegItems particles.
 constexpr int kSegThreads = 256;
-constexpr int kSegRange = 512;
+constexpr int kSegItems = 8;
+constexpr int kSegRange = kWave * kSegItems;                           // 512
 constexpr int kSegBlockParticles = (kSegThreads / kWave) * kSegRange;  // 2048
 
-// Resampling: tiles of the joint particle array.
+// Resampling: tiles of persistent particles, then tiles of new-born slots.
 constexpr int kResThreads = 256;
 constexpr int kResItems = 8;
 constexpr int kResTile = kResThreads * kResItems;  // 2048
@@ -50,22 +61,24 @@ struct GridDev {
     uint32_t C, nu, nb;
     float r, dt, p_s, p_b, sig_pos, sig_vel, sig_birth, alpha;
     uint32_t seed_lo, seed_hi, grid_id;
-    uint32_t n_sort_tiles, n_res_tiles;
-    // persistent particles (start of a cycle / after resampling)
+    // sort plan (from the largest key, C) and tilings
+    uint32_t passes;
+    uint32_t dshift[kMaxPasses], dbits[kMaxPasses];
+    uint32_t n_sort_tiles, n_hist_tiles, n_cell_parts, n_res_ptiles, n_res_btiles;
+    // persistent particles (start of a cycle / after resampling) and their cell keys
     float *x, *y, *vx, *vy, *w;
     uint32_t* key;
-    // sorted particles
+    // particles sorted by cell
     float *sx, *sy, *svx, *svy, *sw;
     uint32_t *skey, *perm;
-    // radix sort scratch
-    uint32_t *tkey, *tval;  // ping-pong partner of (skey, perm)
-    uint32_t* hist;         // digit-major counts, 2^kMaxDigitBits * n_sort_tiles
+    // ping-pong partner of the sorted arrays during the sort
+    float *tx, *ty, *tvx, *tvy, *tw;
+    uint32_t *tkey, *tval;
     // cells
     uint32_t *cstart, *cend;
     double *sum_w, *sum_wt;
     float *m_pO, *m_pF, *m_O, *m_F, *rho_b, *rho_p, *pign;
     double *mu_A, *mu_UA;
-    uint64_t* born_q;  // fixed-point rho_b, then its exclusive prefix sum
     uint32_t* born_off;
     float *mean_x, *mean_y, *var_x, *var_y, *cov_xy;
     uint8_t* mflag;
@@ -73,18 +86,20 @@ struct GridDev {
     float *bx, *by, *bvx, *bvy, *bw;
     uint32_t* bkey;
     uint8_t* bassoc;
-    // resampling scratch
-    uint64_t* res_tile;  // per-tile weight sums, then their exclusive prefix
-    int32_t* res_last;   // per-tile last positive-weight index
-    // generic scan scratch (per-tile partial sums)
-    uint64_t* scan_part;
-    // device scalars
+    // per-cycle scratch: digit histograms of 1024-key sub-tiles (digit-major,
+    // [kSortBins][n_hist_tiles]) with their row totals, fixed-point partial sums of new-born
+    // masses (per 256 cells) and joint weights (per resampling tile), and the first slot of
+    // every cell with births (its cell id, kNoCell elsewhere)
+    uint32_t *hist, *rowtot;
+    uint64_t *bpart, *rpart;
+    uint32_t* born_mark;
+    // device scalars: the cycle to run next (advanced by the resampling) and the cycle being
+    // run (set by the prediction); every writer of either stores one and the same value
     uint32_t* cycle;
+    uint32_t* cycle_run;
     uint32_t* status;
     uint64_t* W_fixed;
     uint64_t* S_fixed;
-    int32_t* last_pos;
-    double* U;
 };
 
 struct MeasDev {
@@ -104,6 +119,19 @@ __device__ __forceinline__ int batch_grid(const Batch& b)
     int gi = 0;
     for (int i = 1; i < b.n; ++i) gi = (blockIdx.x >= b.bstart[i]) ? i : gi;
     return gi;
+}
+
+// Workgroups are dealt to the eight XCDs (each with its own L2) in turn.  For kernels whose
+// neighbouring tiles share data (adjacent output runs, overlapping inputs), each grid's blocks
+// are padded to a multiple of 8 and block i of XCD slot i % 8 takes tile (i % 8) * per + i / 8:
+// every XCD walks one contiguous run of tiles.  Returns a tile >= the grid's tile count for
+// padding blocks, which exit.
+constexpr uint32_t kXcds = 8;
+__device__ __forceinline__ uint32_t xcd_tile(const Batch& b, int gi)
+{
+    const uint32_t lb = blockIdx.x - b.bstart[gi];
+    const uint32_t per = (b.bstart[gi + 1] - b.bstart[gi]) / kXcds;
+    return (lb % kXcds) * per + lb / kXcds;
 }
 
 // --------------------------------------------------------------------------------------------
@@ -167,48 +195,65 @@ __device__ __forceinline__ uint64_t fixed40(float m)
 }
 
 // --------------------------------------------------------------------------------------------
-// Wave-level helpers (wave64).
+// Wave- and block-level helpers (wave64).
 // --------------------------------------------------------------------------------------------
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
 
-__device__ __forceinline__ uint64_t wave_incl_scan_u64(uint64_t v)
+template <typename T>
+__device__ __forceinline__ T wave_incl_scan(T v)
 {
     const int lane = lane_id();
 #pragma unroll
     for (int off = 1; off < kWave; off <<= 1) {
-        const uint64_t o = __shfl_up(v, off, kWave);
+        const T o = __shfl_up(v, off, kWave);
         if (lane >= off) v += o;
     }
     return v;
 }
 
-__device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t v)
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v)
 {
-    const int lane = lane_id();
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+__device__ __forceinline__ int32_t wave_max(int32_t v)
+{
 #pragma unroll
     for (int off = 1; off < kWave; off <<= 1) {
-        const uint32_t o = __shfl_up(v, off, kWave);
-        if (lane >= off) v += o;
+        const int32_t o = __shfl_xor(v, off, kWave);
+        v = o > v ? o : v;
     }
     return v;
 }
 
-// Block-wide exclusive scan of one value per thread (blockDim.x = nthreads, multiple of 64).
-// `lds` must hold nthreads/64 + 1 entries.  Returns the exclusive prefix; *total receives the
-// block total.  Contains __syncthreads().
+// Adds this wave's count of every digit to cnt[d]: lanes holding the same digit find each other
+// with one ballot per digit bit, and the lowest of them adds their number.
+__device__ __forceinline__ void wave_digit_count(bool valid, uint32_t d, uint32_t bits,
+                                                 uint32_t* cnt)
+{
+    uint64_t peers = __ballot(valid);
+    for (uint32_t bit = 0; bit < bits; ++bit) {
+        const bool set = (d >> bit) & 1u;
+        const uint64_t bb = __ballot(set);
+        peers &= set ? bb : ~bb;
+    }
+    const uint64_t lt = (1ull << lane_id()) - 1ull;
+    if (valid && (peers & lt) == 0) cnt[d] += (uint32_t)__popcll(peers);
+}
+
+// Block-wide exclusive scan of one value per thread (blockDim.x a multiple of 64).  `lds` must
+// hold blockDim.x/64 + 1 entries.  Returns the exclusive prefix; *total gets the block total.
 template <typename T>
 __device__ __forceinline__ T block_excl_scan(T v, T* lds, T* total)
 {
     const int lane = lane_id();
     const int wave = threadIdx.x / kWave;
     const int nwaves = blockDim.x / kWave;
-    T incl = v;
-#pragma unroll
-    for (int off = 1; off < kWave; off <<= 1) {
-        const T o = __shfl_up(incl, off, kWave);
-        if (lane >= off) incl += o;
-    }
+    const T incl = wave_incl_scan(v);
     if (lane == kWave - 1) lds[wave] = incl;
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -225,6 +270,15 @@ __device__ __forceinline__ T block_excl_scan(T v, T* lds, T* total)
     *total = lds[nwaves];
     __syncthreads();
     return res;
+}
+
+// Block-wide sum (result valid in every thread).
+template <typename T>
+__device__ __forceinline__ T block_sum(T v, T* lds)
+{
+    T total;
+    block_excl_scan(v, lds, &total);
+    return total;
 }
 
 }  // namespace dogm

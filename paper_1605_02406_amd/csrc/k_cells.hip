@@ -1,23 +1,46 @@
-// Per-cell work: sums over each cell's particles (Alg. 3 and 4), the Dempster-Shafer cell
-// update with the new-born split (Alg. 3) and the velocity moments (Alg. 6).
+// Per-cell work over the sorted particles: the particle range of every cell (Alg. 2), the
+// Dempster-Shafer cell update with the new-born split (Alg. 3), the normalisation components of
+// the persistent update (Alg. 4) and the velocity moments (Alg. 6).
 //
 // Per-cell sums are segmented reductions over the sorted particles instead of the paper's
 // prefix-sum differences (a global FP32 prefix loses the digits of late cells).  Each wave owns
-// a range of kSegRange particles and sums every cell whose first particle lies in that range,
-// reading past the range end to finish its last cell; 64 particles at a time it runs a
-// segmented inclusive scan across lanes (keys are sorted, so lanes with equal keys are
-// contiguous) and carries the running sum of the last cell into the next chunk.  Accumulators
-// are FP64 and the summation order depends only on the data, never on the launch.
+// 64 * kSegItems particles and every cell whose first particle lies there, reading on past its
+// range to finish its last cell.  Within a chunk each lane adds up kSegItems consecutive
+// particles, closing the cells that end inside it, and one segmented scan across the lanes joins
+// the cells that span lanes; the running sum of a cell still open at the end of the chunk is
+// carried into the next one.  Accumulators are FP64 and the summation order depends only on the
+// data, never on the launch or the batch.  The same pass records where each cell's particles
+// start and end.
+//
+// Without velocity evidence (p_A = 0) the updated persistent weights are w' = mu_UA w, so the
+// velocity moments of the updated particles, normalised by rho_p = mu_UA sum w, equal the plain
+// weighted moments of the predicted ones: the same pass that sums the weights also sums w v,
+// w v^2 and w vx vy, and the cell's last lane writes masses and moments together.  With velocity
+// evidence the moments need the updated weights and take a pass of their own.
 #include "launch.h"
 
 namespace dogm {
 
+constexpr uint32_t kNone = 0xFFFFFFFFu;
+
+// First index in [from, to) whose key differs from `key` (to if none), found 64 keys at a time.
+__device__ __forceinline__ uint32_t first_other(const uint32_t* skey, uint32_t from, uint32_t to,
+                                                uint32_t key)
+{
+    for (uint32_t base = from; base < to; base += kWave) {
+        const uint32_t i = base + lane_id();
+        const uint64_t m = __ballot(i < to && skey[i] != key);
+        if (m) return base + (uint32_t)(__ffsll((unsigned long long)m) - 1);
+    }
+    return to;
+}
+
 // One wave's share of a segmented reduction with NV FP64 sums per particle.
-//   load(i, k, v): fill v[0..NV) for sorted particle i of cell k
-//   emit(k, v)   : the complete sums of cell k
-template <int NV, typename Load, typename Emit>
-__device__ __forceinline__ void seg_reduce_wave(const GridDev& G, uint32_t wave_index, Load load,
-                                                Emit emit)
+//   val(k, w, vx, vy, v): v[0..NV) of a particle of cell k with weight w and velocity (vx, vy)
+//   emit(k, v)          : the complete sums of cell k (called once per cell, by one lane)
+template <int NV, typename Val, typename Emit>
+__device__ __forceinline__ void seg_reduce(const GridDev& G, uint32_t wave_index, Val val,
+                                           Emit emit)
 {
     const int lane = lane_id();
     const uint32_t n = G.nu, C = G.C;
@@ -26,61 +49,127 @@ __device__ __forceinline__ void seg_reduce_wave(const GridDev& G, uint32_t wave_
     const uint32_t b = min(a + (uint32_t)kSegRange, n);
     const uint32_t ka = G.skey[a];
     if (ka >= C) return;  // only particles outside the grid from here on
-    uint32_t p0 = a;
-    if (a > 0 && G.skey[a - 1] == ka) p0 = G.cend[ka];  // that cell belongs to an earlier wave
+    // skip the cell that began before a (an earlier wave owns it); finish the cell holding b - 1
+    const uint32_t p0 = (a > 0 && G.skey[a - 1] == ka) ? first_other(G.skey, a, b, ka) : a;
     if (p0 >= b) return;
     const uint32_t kl = G.skey[b - 1];
-    const uint32_t pend = (kl < C) ? max(b, G.cend[kl]) : b;
+    const uint32_t pend = (kl < C && b < n) ? first_other(G.skey, b, n, kl) : b;
 
     double carry[NV];
 #pragma unroll
     for (int j = 0; j < NV; ++j) carry[j] = 0.0;
-    uint32_t carry_key = 0xFFFFFFFFu;
+    uint32_t carry_key = kNone, prev_chunk_tail = kNone;
 
-    for (uint32_t base = p0; base < pend; base += kWave) {
-        const uint32_t i = base + lane;
-        uint32_t k = (i < pend) ? G.skey[i] : 0xFFFFFFFFu;
-        if (k >= C) k = 0xFFFFFFFFu;
-        const bool valid = k != 0xFFFFFFFFu;
-        double v[NV];
-        if (valid) {
-            load(i, k, v);
-        } else {
+    for (uint32_t base = p0; base < pend; base += kSegRange) {
+        // this lane's run of kSegItems particles: loads first
+        const uint32_t i0 = base + lane * kSegItems;
+        uint32_t key[kSegItems];
+        float pw[kSegItems], pvx[kSegItems], pvy[kSegItems];
 #pragma unroll
-            for (int j = 0; j < NV; ++j) v[j] = 0.0;
+        for (int it = 0; it < kSegItems; ++it) {
+            const uint32_t i = i0 + it;
+            const uint32_t k = (i < pend) ? G.skey[i] : kNone;
+            key[it] = k >= C ? kNone : k;
         }
 #pragma unroll
-        for (int off = 1; off < kWave; off <<= 1) {
-            const uint32_t ko = __shfl_up(k, off, kWave);
+        for (int it = 0; it < kSegItems; ++it) {
+            const uint32_t i = i0 + it;
+            const bool ok = key[it] != kNone;
+            pw[it] = ok ? G.sw[i] : 0.0f;
+            pvx[it] = ok ? G.svx[i] : 0.0f;
+            pvy[it] = ok ? G.svy[i] : 0.0f;
+        }
+        const uint32_t first = key[0];
+        uint32_t cur = key[0];
+        bool multi = false;
+        double head[NV], acc[NV];
 #pragma unroll
-            for (int j = 0; j < NV; ++j) {
-                const double o = __shfl_up(v[j], off, kWave);
-                if (lane >= off && ko == k) v[j] += o;
+        for (int j = 0; j < NV; ++j) head[j] = acc[j] = 0.0;
+#pragma unroll
+        for (int it = 0; it < kSegItems; ++it) {
+            const uint32_t k = key[it];
+            if (it > 0 && k != cur) {  // the cell `cur` ends inside this lane
+                if (cur != kNone) G.cend[cur] = i0 + it;
+                if (k != kNone) G.cstart[k] = i0 + it;
+                if (!multi) {
+#pragma unroll
+                    for (int j = 0; j < NV; ++j) head[j] = acc[j];
+                    multi = true;
+                } else if (cur != kNone) {
+                    emit(cur, acc);  // began and ended inside this lane
+                }
+#pragma unroll
+                for (int j = 0; j < NV; ++j) acc[j] = 0.0;
+                cur = k;
+            }
+            if (k != kNone) {
+                double v[NV];
+                val(k, pw[it], pvx[it], pvy[it], v);
+#pragma unroll
+                for (int j = 0; j < NV; ++j) acc[j] += v[j];
             }
         }
-        if (valid && k == carry_key) {
+        const uint32_t prev_tail = __shfl_up(cur, 1, kWave);
+        // a cell starts at this lane's first particle unless the previous particle is its own
+        const uint32_t before_first =
+            lane == 0 ? (base == p0 ? kNone : prev_chunk_tail) : prev_tail;
+        if (first != kNone && before_first != first) G.cstart[first] = i0;
+        // the cell carried in from the previous chunk continues in lane 0
+        if (lane == 0 && first != kNone && first == carry_key) {
+            if (multi) {
 #pragma unroll
-            for (int j = 0; j < NV; ++j) v[j] += carry[j];
+                for (int j = 0; j < NV; ++j) head[j] += carry[j];
+            } else {
+#pragma unroll
+                for (int j = 0; j < NV; ++j) acc[j] += carry[j];
+            }
         }
-        // key of the next particle: the next lane, or for the last lane the next chunk
-        uint32_t knext = __shfl_down(k, 1, kWave);
+        // join the tail cells across lanes: a lane's tail continues the previous lane's tail
+        // when the lane holds a single cell equal to it
+        bool start = lane == 0 || multi || prev_tail != cur || cur == kNone;
+        double run[NV];
+#pragma unroll
+        for (int j = 0; j < NV; ++j) run[j] = acc[j];
+#pragma unroll
+        for (int off = 1; off < kWave; off <<= 1) {
+            const bool so = __shfl_up(start ? 1 : 0, off, kWave) != 0;
+#pragma unroll
+            for (int j = 0; j < NV; ++j) {
+                const double o = __shfl_up(run[j], off, kWave);
+                if (lane >= off && !start) run[j] += o;
+            }
+            if (lane >= off && !start) start = so;
+        }
+        // a multi-cell lane closes its head cell, joined with the previous lane's tail
+        double prev_run[NV];
+#pragma unroll
+        for (int j = 0; j < NV; ++j) prev_run[j] = __shfl_up(run[j], 1, kWave);
+        if (multi && first != kNone) {
+            if (lane > 0 && prev_tail == first) {
+#pragma unroll
+                for (int j = 0; j < NV; ++j) head[j] += prev_run[j];
+            }
+            emit(first, head);
+        }
+        // a tail cell ends here unless the next lane (or the next chunk) continues it
+        uint32_t next_first = __shfl_down(first, 1, kWave);
         if (lane == kWave - 1) {
-            knext = (i + 1 < pend) ? G.skey[i + 1] : 0xFFFFFFFFu;
-            if (knext >= C) knext = 0xFFFFFFFFu;
+            const uint32_t inext = base + kSegRange;
+            next_first = (inext < pend) ? G.skey[inext] : kNone;
+            if (next_first >= C) next_first = kNone;
         }
-        if (valid && knext != k) emit(k, v);
-        // the cell still open at the end of the chunk continues in the next one
-        const uint32_t klast = __shfl(k, kWave - 1, kWave);
-        const uint32_t knl = __shfl(knext, kWave - 1, kWave);
-        carry_key = (klast != 0xFFFFFFFFu && knl == klast) ? klast : 0xFFFFFFFFu;
+        if (cur != kNone && next_first != cur) {
+            G.cend[cur] = i0 + kSegItems;
+            emit(cur, run);
+        }
+        const uint32_t t63 = __shfl(cur, kWave - 1, kWave);
+        const uint32_t n63 = __shfl(next_first, kWave - 1, kWave);
+        carry_key = (t63 != kNone && n63 == t63) ? t63 : kNone;
+        prev_chunk_tail = t63;
 #pragma unroll
-        for (int j = 0; j < NV; ++j) carry[j] = __shfl(v[j], kWave - 1, kWave);
+        for (int j = 0; j < NV; ++j) carry[j] = __shfl(run[j], kWave - 1, kWave);
     }
 }
-
-// ----------------------------------------------------------------------------------------------
-// Alg. 3 (sums) and Alg. 4 (sums of w~ = g w): per-cell FP64 sums of the predicted weights.
-// ----------------------------------------------------------------------------------------------
 
 __device__ __forceinline__ double likelihood(double vx, double vy, double mx, double my,
                                              double var)
@@ -89,48 +178,14 @@ __device__ __forceinline__ double likelihood(double vx, double vy, double mx, do
     return exp(-(dx * dx + dy * dy) / (2.0 * var));
 }
 
-template <bool kAssoc>
-__global__ __launch_bounds__(kSegThreads) void k_seg_weights(Batch b)
-{
-    const int gi = batch_grid(b);
-    const GridDev& G = *b.g[gi];
-    const MeasDev& M = b.m[gi];
-    const uint32_t wave = (blockIdx.x - b.bstart[gi]) * (kSegThreads / kWave) + threadIdx.x / kWave;
-    if (kAssoc) {
-        seg_reduce_wave<2>(
-            G, wave,
-            [&](uint32_t i, uint32_t k, double* v) {
-                const double w = (double)G.sw[i];
-                v[0] = w;
-                v[1] = likelihood((double)G.svx[i], (double)G.svy[i], (double)M.mu_vx[k],
-                                  (double)M.mu_vy[k], (double)M.var_v[k]) * w;
-            },
-            [&](uint32_t k, const double* v) {
-                G.sum_w[k] = v[0];
-                G.sum_wt[k] = v[1];
-            });
-    } else {
-        seg_reduce_wave<1>(
-            G, wave, [&](uint32_t i, uint32_t, double* v) { v[0] = (double)G.sw[i]; },
-            [&](uint32_t k, const double* v) { G.sum_w[k] = v[0]; });
-    }
-}
-
 // Per cell, FP64: predicted BBA (eqs. (DS_particle_sum_pred), (DS_freespace_pred)), Dempster
 // combination with the measurement (eq. (DS_comb)), new-born split (eqs.
-// (DS_resulting_masses1/2), new-born mass only where m_z(O) > 0), normalisation components
-// (eqs. (DSnormalizationfactor), (DSnormalizationfactor2)) and the fixed-point new-born mass.
-__global__ __launch_bounds__(kElemThreads) void k_cell_update(Batch b)
+// (DS_resulting_masses1/2), new-born mass only where m_z(O) > 0) and the normalisation
+// components (eqs. (DSnormalizationfactor), (DSnormalizationfactor2)).  s = sum of predicted
+// weights, st = sum of g w.  Returns rho_p (also stored).
+__device__ __forceinline__ double cell_update(const GridDev& G, const MeasDev& M, uint32_t c,
+                                              double s, double st)
 {
-    const int gi = batch_grid(b);
-    const GridDev& G = *b.g[gi];
-    const MeasDev& M = b.m[gi];
-    const uint32_t c = (blockIdx.x - b.bstart[gi]) * kElemThreads + threadIdx.x;
-    if (c >= G.C) return;
-    const bool nonempty = G.cend[c] > G.cstart[c];
-    const double s = nonempty ? G.sum_w[c] : 0.0;
-    if (!nonempty) G.sum_w[c] = 0.0;
-    const double st = (nonempty && M.p_assoc != nullptr) ? G.sum_wt[c] : 0.0;
     const double po = s < 1.0 ? s : 1.0;
     const double pf_cand = (double)G.alpha * (double)G.m_F[c];
     const double pf = pf_cand < 1.0 - po ? pf_cand : 1.0 - po;
@@ -156,113 +211,171 @@ __global__ __launch_bounds__(kElemThreads) void k_cell_update(Batch b)
         rb = den > 0.0 ? o * a / den : 0.0;
     }
     const double rp = o - rb;
-    const double mu_ua = s > 0.0 ? rp / s : 0.0;
-    const double mu_a = st > 0.0 ? rp / st : 0.0;
     if (!isfinite(o) || !isfinite(f) || !isfinite(s)) st_bits |= kStNonFinite;
-    const float rbf = (float)rb;
+    G.sum_w[c] = s;
+    G.sum_wt[c] = st;
     G.m_pO[c] = (float)po;
     G.m_pF[c] = (float)pf;
     G.m_O[c] = (float)o;
     G.m_F[c] = (float)f;
-    G.rho_b[c] = rbf;
+    G.rho_b[c] = (float)rb;
     G.rho_p[c] = (float)rp;
     G.pign[c] = (float)(o + 0.5 * (1.0 - o - f));
-    G.mu_UA[c] = mu_ua;
-    G.mu_A[c] = mu_a;
-    G.born_q[c] = fixed40(rbf);
+    G.mu_UA[c] = s > 0.0 ? rp / s : 0.0;
+    G.mu_A[c] = st > 0.0 ? rp / st : 0.0;
     if (st_bits) atomicOr(G.status, st_bits);
+    return rp;
 }
 
-hipError_t launch_cell_update(const GridRef* g, int n, hipStream_t s)
+// Moments are defined where the stored rho_p is positive and the cell holds particles (the
+// caller knows the latter); sums over weights that are all zero give zero moments.
+__device__ __forceinline__ void write_moments(const GridDev& G, uint32_t c, bool defined,
+                                              double norm, double sx, double sy, double sxx,
+                                              double syy, double sxy)
 {
-    Batch b;
-    uint32_t blocks =
-        make_batch(b, g, n, [](const GridDev& G) { return ceil_div(G.nu, kSegBlockParticles); });
+    if (!defined || !(norm > 0.0)) {
+        G.mean_x[c] = G.mean_y[c] = G.var_x[c] = G.var_y[c] = G.cov_xy[c] = 0.0f;
+        G.mflag[c] = defined ? 1 : 0;
+        return;
+    }
+    const double mx = sx / norm, my = sy / norm;
+    G.mean_x[c] = (float)mx;
+    G.mean_y[c] = (float)my;
+    G.var_x[c] = (float)(sxx / norm - mx * mx);
+    G.var_y[c] = (float)(syy / norm - my * my);
+    G.cov_xy[c] = (float)(sxy / norm - mx * my);
+    G.mflag[c] = 1;
+}
+
+// ----------------------------------------------------------------------------------------------
+// Alg. 3 + 4 (+ 6 without velocity evidence) on the cells that hold particles.
+// ----------------------------------------------------------------------------------------------
+
+template <bool kAssoc>
+__global__ __launch_bounds__(kSegThreads) void k_seg_update(Batch b)
+{
+    const int gi = batch_grid(b);
+    const GridDev& G = *b.g[gi];
+    const MeasDev& M = b.m[gi];
+    const uint32_t tile = xcd_tile(b, gi);
+    const uint32_t wave = tile * (kSegThreads / kWave) + threadIdx.x / kWave;
+    if (kAssoc) {
+        seg_reduce<2>(
+            G, wave,
+            [&](uint32_t k, float w, float vx, float vy, double* v) {
+                v[0] = (double)w;
+                v[1] = likelihood((double)vx, (double)vy, (double)M.mu_vx[k],
+                                  (double)M.mu_vy[k], (double)M.var_v[k]) * (double)w;
+            },
+            [&](uint32_t k, const double* v) { cell_update(G, M, k, v[0], v[1]); });
+    } else {
+        seg_reduce<6>(
+            G, wave,
+            [&](uint32_t, float w, float vx, float vy, double* v) {
+                const double wd = (double)w, x = (double)vx, y = (double)vy;
+                v[0] = wd;
+                v[1] = wd * x;
+                v[2] = wd * y;
+                v[3] = wd * x * x;
+                v[4] = wd * y * y;
+                v[5] = wd * x * y;
+            },
+            [&](uint32_t k, const double* v) {
+                const double rp = cell_update(G, M, k, v[0], 0.0);
+                // moments of the updated weights mu_UA w, normalised by rho_p = mu_UA sum w
+                write_moments(G, k, (float)rp > 0.0f, v[0], v[1], v[2], v[3], v[4], v[5]);
+            });
+    }
+}
+
+// Empty cells: no predicted mass, the same update with sum w = 0, moments undefined.  Every
+// block also stores the fixed-point new-born mass of its cells (all of them; the non-empty ones
+// were updated by the previous kernel).
+__global__ __launch_bounds__(kCellThreads) void k_cells_empty(Batch b)
+{
+    __shared__ uint64_t tmp[kCellThreads / kWave + 1];
+    const int gi = batch_grid(b);
+    const GridDev& G = *b.g[gi];
+    const MeasDev& M = b.m[gi];
+    const uint32_t part = blockIdx.x - b.bstart[gi];
+    const uint32_t c = part * kCellThreads + threadIdx.x;
+    uint64_t q = 0;
+    if (c < G.C) {
+        if (G.cend[c] == G.cstart[c]) {
+            cell_update(G, M, c, 0.0, 0.0);
+            write_moments(G, c, false, 0, 0, 0, 0, 0, 0);
+        }
+        q = fixed40(G.rho_b[c]);
+    }
+    const uint64_t qsum = block_sum(q, tmp);
+    if (threadIdx.x == 0) G.bpart[part] = qsum;
+}
+
+hipError_t launch_update(const GridRef* g, int n, hipStream_t s)
+{
     bool any_assoc = false, all_assoc = true;
     for (int i = 0; i < n; ++i) {
         any_assoc |= g[i].m.p_assoc != nullptr;
         all_assoc &= g[i].m.p_assoc != nullptr;
     }
     if (any_assoc && !all_assoc) return hipErrorInvalidValue;  // one kind per launch
+    Batch b;
+    uint32_t blocks = make_batch(b, g, n, [](const GridDev& G) {
+        return xcd_blocks(ceil_div(G.nu, kSegBlockParticles));
+    });
     if (blocks) {
         if (any_assoc)
-            hipLaunchKernelGGL(k_seg_weights<true>, dim3(blocks), dim3(kSegThreads), 0, s, b);
+            DOGM_LAUNCH(k_seg_update<true>, dim3(blocks), dim3(kSegThreads), 0, s, b);
         else
-            hipLaunchKernelGGL(k_seg_weights<false>, dim3(blocks), dim3(kSegThreads), 0, s, b);
+            DOGM_LAUNCH(k_seg_update<false>, dim3(blocks), dim3(kSegThreads), 0, s, b);
     }
-    blocks = make_batch(b, g, n, [](const GridDev& G) { return ceil_div(G.C, kElemThreads); });
-    if (blocks) hipLaunchKernelGGL(k_cell_update, dim3(blocks), dim3(kElemThreads), 0, s, b);
-    return hipGetLastError();
+    blocks = make_batch(b, g, n, [](const GridDev& G) { return G.n_cell_parts; });
+    if (blocks) DOGM_LAUNCH(k_cells_empty, dim3(blocks), dim3(kCellThreads), 0, s, b);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = launch_born_offsets(g, n, s);
+    if (e == hipSuccess) e = launch_particle_tiles(g, n, s);
+    return e;
 }
 
 // ----------------------------------------------------------------------------------------------
-// Alg. 6: velocity moments.  Sums are shifted by the velocity (a, b) of the cell's first
-// particle:  S0 = sum w, S1 = sum w (vx - a), S2 = sum w (vy - b), S3 = sum w (vx - a)^2,
-// S4 = sum w (vy - b)^2, S5 = sum w (vx - a)(vy - b).  With s = S0 / rho_p and
-// d_x = S1 / rho_p + a (s - 1) these give exactly the printed moments
-//   mean_x = a + d_x,   var_x = S3 / rho_p - d_x^2 - a^2 (s - 1),
-//   cov_xy = S5 / rho_p - d_x d_y - a b (s - 1),
-// without the cancellation of E[v^2] - mean^2.
+// Alg. 6 with velocity evidence: moments of the updated weights, normalised by rho_p.
 // ----------------------------------------------------------------------------------------------
 
 __global__ __launch_bounds__(kSegThreads) void k_seg_moments(Batch b)
 {
     const int gi = batch_grid(b);
     const GridDev& G = *b.g[gi];
-    const uint32_t wave = (blockIdx.x - b.bstart[gi]) * (kSegThreads / kWave) + threadIdx.x / kWave;
-    seg_reduce_wave<6>(
+    const uint32_t tile = xcd_tile(b, gi);
+    const uint32_t wave = tile * (kSegThreads / kWave) + threadIdx.x / kWave;
+    seg_reduce<5>(
         G, wave,
-        [&](uint32_t i, uint32_t k, double* v) {
-            const uint32_t h = G.cstart[k];
-            const double w = (double)G.sw[i];
-            const double dx = (double)G.svx[i] - (double)G.svx[h];
-            const double dy = (double)G.svy[i] - (double)G.svy[h];
-            v[0] = w;
-            v[1] = w * dx;
-            v[2] = w * dy;
-            v[3] = w * dx * dx;
-            v[4] = w * dy * dy;
-            v[5] = w * dx * dy;
+        [&](uint32_t, float w, float vx, float vy, double* v) {
+            const double wd = (double)w, x = (double)vx, y = (double)vy;
+            v[0] = wd * x;
+            v[1] = wd * y;
+            v[2] = wd * x * x;
+            v[3] = wd * y * y;
+            v[4] = wd * x * y;
         },
         [&](uint32_t k, const double* v) {
             const double rp = (double)G.rho_p[k];
-            if (!(rp > 0.0)) {
-                G.mean_x[k] = G.mean_y[k] = G.var_x[k] = G.var_y[k] = G.cov_xy[k] = 0.0f;
-                G.mflag[k] = 0;
-                return;
-            }
-            const uint32_t h = G.cstart[k];
-            const double a = (double)G.svx[h], bb = (double)G.svy[h];
-            const double sm1 = (v[0] - rp) / rp;  // s - 1
-            const double dx = v[1] / rp + a * sm1;
-            const double dy = v[2] / rp + bb * sm1;
-            G.mean_x[k] = (float)(a + dx);
-            G.mean_y[k] = (float)(bb + dy);
-            G.var_x[k] = (float)(v[3] / rp - dx * dx - a * a * sm1);
-            G.var_y[k] = (float)(v[4] / rp - dy * dy - bb * bb * sm1);
-            G.cov_xy[k] = (float)(v[5] / rp - dx * dy - a * bb * sm1);
-            G.mflag[k] = 1;
+            write_moments(G, k, rp > 0.0, rp, v[0], v[1], v[2], v[3], v[4]);
         });
-}
-
-__global__ __launch_bounds__(kElemThreads) void k_moments_empty(Batch b)
-{
-    const int gi = batch_grid(b);
-    const GridDev& G = *b.g[gi];
-    const uint32_t c = (blockIdx.x - b.bstart[gi]) * kElemThreads + threadIdx.x;
-    if (c >= G.C || G.cend[c] > G.cstart[c]) return;
-    G.mean_x[c] = G.mean_y[c] = G.var_x[c] = G.var_y[c] = G.cov_xy[c] = 0.0f;
-    G.mflag[c] = 0;
 }
 
 hipError_t launch_moments(const GridRef* g, int n, hipStream_t s)
 {
+    // without velocity evidence the update already wrote the moments
+    GridRef sub[kMaxBatch];
+    int m = 0;
+    for (int i = 0; i < n; ++i)
+        if (g[i].m.p_assoc != nullptr) sub[m++] = g[i];
+    if (m == 0) return hipSuccess;
     Batch b;
-    uint32_t blocks =
-        make_batch(b, g, n, [](const GridDev& G) { return ceil_div(G.nu, kSegBlockParticles); });
-    if (blocks) hipLaunchKernelGGL(k_seg_moments, dim3(blocks), dim3(kSegThreads), 0, s, b);
-    blocks = make_batch(b, g, n, [](const GridDev& G) { return ceil_div(G.C, kElemThreads); });
-    if (blocks) hipLaunchKernelGGL(k_moments_empty, dim3(blocks), dim3(kElemThreads), 0, s, b);
+    const uint32_t blocks = make_batch(b, sub, m, [](const GridDev& G) {
+        return xcd_blocks(ceil_div(G.nu, kSegBlockParticles));
+    });
+    if (blocks) DOGM_LAUNCH(k_seg_moments, dim3(blocks), dim3(kSegThreads), 0, s, b);
     return hipGetLastError();
 }
 

@@ -1,6 +1,6 @@
-// Element-wise particle kernels: descriptor upload, initial state, prediction (Alg. 1), the
-// gather into cell order with per-cell ranges (Alg. 2), the persistent weight update (Alg. 4)
-// and the new-born particles (Alg. 5).
+// Element-wise kernels: descriptor upload, initial state, prediction (Alg. 1) with the digit
+// histogram of the sort's first pass, the new-born slot allocation and initialisation of
+// Alg. 5 and the last loop of Alg. 4 (weight normalisation).
 #include "launch.h"
 
 namespace dogm {
@@ -9,7 +9,7 @@ __global__ void k_write_desc(GridDev hd, GridDev* dd) { *dd = hd; }
 
 hipError_t launch_write_desc(const GridDev& hd, GridDev* dd, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_write_desc, dim3(1), dim3(1), 0, s, hd, dd);
+    DOGM_LAUNCH(k_write_desc, dim3(1), dim3(1), 0, s, hd, dd);
     return hipGetLastError();
 }
 
@@ -35,6 +35,7 @@ __global__ __launch_bounds__(kElemThreads) void k_init(Batch b)
     if (i < G.C) G.m_F[i] = 0.0f;
     if (i == 0) {
         *G.cycle = 1u;
+        *G.cycle_run = 1u;
         *G.status = 0u;
         *G.W_fixed = 0;
         *G.S_fixed = 0;
@@ -47,162 +48,117 @@ hipError_t launch_init(const GridRef* g, int n, hipStream_t s)
     const uint32_t blocks = make_batch(b, g, n, [](const GridDev& G) {
         return ceil_div(G.nu > G.C ? G.nu : G.C, kElemThreads);
     });
-    if (blocks) hipLaunchKernelGGL(k_init, dim3(blocks), dim3(kElemThreads), 0, s, b);
+    if (blocks) DOGM_LAUNCH(k_init, dim3(blocks), dim3(kElemThreads), 0, s, b);
     return hipGetLastError();
 }
 
 __global__ void k_set_cycle(Batch b, uint32_t cycle)
 {
-    if (threadIdx.x == 0) *b.g[blockIdx.x]->cycle = cycle;
+    if (threadIdx.x == 0) {
+        *b.g[blockIdx.x]->cycle = cycle;
+        *b.g[blockIdx.x]->cycle_run = cycle;
+    }
 }
 
 hipError_t launch_set_cycle(const GridRef* g, int n, uint32_t cycle, hipStream_t s)
 {
     Batch b;
     make_batch(b, g, n, [](const GridDev&) { return 1u; });
-    hipLaunchKernelGGL(k_set_cycle, dim3(n), dim3(64), 0, s, b, cycle);
+    DOGM_LAUNCH(k_set_cycle, dim3(n), dim3(64), 0, s, b, cycle);
     return hipGetLastError();
 }
 
 // ----------------------------------------------------------------------------------------------
-// Alg. 1: constant-velocity prediction with Philox noise, persistence, cell key.
+// Alg. 1: constant-velocity prediction with Philox noise, persistence, cell key.  One block per
+// 1024 particles: it also stores its digit histogram for the sort's first pass.  The blocks
+// also clear what later kernels fill in sparsely (cell ranges, first-slot marks) and record the
+// cycle being run.
 // ----------------------------------------------------------------------------------------------
+
+constexpr int kPredItems = kHistTile / kElemThreads;  // 4
 
 __global__ __launch_bounds__(kElemThreads) void k_predict(Batch b)
 {
+    __shared__ uint32_t cnt[kElemThreads / kWave][kSortBins];
     const int gi = batch_grid(b);
     const GridDev& G = *b.g[gi];
-    const uint32_t i = (blockIdx.x - b.bstart[gi]) * kElemThreads + threadIdx.x;
-    if (i >= G.nu) return;
+    const uint32_t tile = xcd_tile(b, gi);
+    if (tile >= G.n_hist_tiles) return;
     const uint32_t cycle = *G.cycle;
-    const uint4 r = draw(G, i, cycle, kPurposePredict);
-    float n0, n1, n2, n3;
-    box_muller_f32(unit_f32(r.x), unit_f32(r.y), n0, n1);
-    box_muller_f32(unit_f32(r.z), unit_f32(r.w), n2, n3);
-    const float x = G.x[i], y = G.y[i], vx = G.vx[i], vy = G.vy[i], w = G.w[i];
-    const float xn = x + G.dt * vx + G.sig_pos * n0;
-    const float yn = y + G.dt * vy + G.sig_pos * n1;
-    const float vxn = vx + G.sig_vel * n2;
-    const float vyn = vy + G.sig_vel * n3;
-    const uint32_t k = cell_of(G, xn, yn);
-    G.x[i] = xn;
-    G.y[i] = yn;
-    G.vx[i] = vxn;
-    G.vy[i] = vyn;
-    G.w[i] = (k == G.C) ? 0.0f : G.p_s * w;
-    G.key[i] = k;
+    const uint32_t shift = G.dshift[0], bits = G.dbits[0], nbins = 1u << bits;
+    const int wave = threadIdx.x / kWave;
+
+    const uint32_t nthreads = G.n_hist_tiles * kElemThreads;
+    const uint32_t tid = tile * kElemThreads + threadIdx.x;
+    for (uint32_t c = tid; c < G.C; c += nthreads) {
+        G.cstart[c] = 0;
+        G.cend[c] = 0;
+    }
+    for (uint32_t s = tid; s < G.nb; s += nthreads) G.born_mark[s] = kNoCell;
+    if (tid == 0) *G.cycle_run = cycle;
+
+    for (uint32_t d = threadIdx.x; d < (kElemThreads / kWave) * nbins; d += kElemThreads)
+        cnt[d / nbins][d % nbins] = 0;
+    __syncthreads();
+
+    float x[kPredItems], y[kPredItems], vx[kPredItems], vy[kPredItems], w[kPredItems];
+#pragma unroll
+    for (int it = 0; it < kPredItems; ++it) {
+        const uint32_t i = tile * kHistTile + it * kElemThreads + threadIdx.x;
+        const bool valid = i < G.nu;
+        x[it] = valid ? G.x[i] : 0.0f;
+        y[it] = valid ? G.y[i] : 0.0f;
+        vx[it] = valid ? G.vx[i] : 0.0f;
+        vy[it] = valid ? G.vy[i] : 0.0f;
+        w[it] = valid ? G.w[i] : 0.0f;
+    }
+#pragma unroll
+    for (int it = 0; it < kPredItems; ++it) {
+        const uint32_t i = tile * kHistTile + it * kElemThreads + threadIdx.x;
+        const bool valid = i < G.nu;
+        uint32_t k = 0;
+        if (valid) {
+            const uint4 r = draw(G, i, cycle, kPurposePredict);
+            float n0, n1, n2, n3;
+            box_muller_f32(unit_f32(r.x), unit_f32(r.y), n0, n1);
+            box_muller_f32(unit_f32(r.z), unit_f32(r.w), n2, n3);
+            const float xn = x[it] + G.dt * vx[it] + G.sig_pos * n0;
+            const float yn = y[it] + G.dt * vy[it] + G.sig_pos * n1;
+            const float vxn = vx[it] + G.sig_vel * n2;
+            const float vyn = vy[it] + G.sig_vel * n3;
+            k = cell_of(G, xn, yn);
+            G.x[i] = xn;
+            G.y[i] = yn;
+            G.vx[i] = vxn;
+            G.vy[i] = vyn;
+            G.w[i] = (k == G.C) ? 0.0f : G.p_s * w[it];
+            G.key[i] = k;
+        }
+        wave_digit_count(valid, (k >> shift) & (nbins - 1u), bits, cnt[wave]);
+    }
+    __syncthreads();
+    for (uint32_t d = threadIdx.x; d < nbins; d += kElemThreads) {
+        uint32_t t = 0;
+        for (int wv = 0; wv < kElemThreads / kWave; ++wv) t += cnt[wv][d];
+        G.hist[d * G.n_hist_tiles + tile] = t;
+    }
 }
 
 hipError_t launch_predict(const GridRef* g, int n, hipStream_t s)
 {
     Batch b;
     const uint32_t blocks =
-        make_batch(b, g, n, [](const GridDev& G) { return ceil_div(G.nu, kElemThreads); });
-    if (blocks) hipLaunchKernelGGL(k_predict, dim3(blocks), dim3(kElemThreads), 0, s, b);
+        make_batch(b, g, n, [](const GridDev& G) { return xcd_blocks(G.n_hist_tiles); });
+    if (blocks) DOGM_LAUNCH(k_predict, dim3(blocks), dim3(kElemThreads), 0, s, b);
     return hipGetLastError();
 }
 
 // ----------------------------------------------------------------------------------------------
-// Alg. 2 (after the sort): particles into cell order; first/last particle of a cell group
-// writes the cell's range.  Cells are cleared first so empty cells read start == end.
+// Alg. 5: slot allocation from the exact prefix E_c of the fixed-point new-born masses; each cell
+// that receives slots marks its first slot with its id.
 // ----------------------------------------------------------------------------------------------
 
-__global__ __launch_bounds__(kElemThreads) void k_clear_cells(Batch b)
-{
-    const int gi = batch_grid(b);
-    const GridDev& G = *b.g[gi];
-    const uint32_t c = (blockIdx.x - b.bstart[gi]) * kElemThreads + threadIdx.x;
-    if (c < G.C) {
-        G.cstart[c] = 0;
-        G.cend[c] = 0;
-    }
-}
-
-__global__ __launch_bounds__(kElemThreads) void k_gather(Batch b)
-{
-    const int gi = batch_grid(b);
-    const GridDev& G = *b.g[gi];
-    const uint32_t s = (blockIdx.x - b.bstart[gi]) * kElemThreads + threadIdx.x;
-    if (s >= G.nu) return;
-    uint32_t src = G.perm[s];
-    if (src >= G.nu) {  // cannot happen for a correct sort; reported, never dereferenced
-        atomicOr(G.status, kStInternal);
-        src = s;
-    }
-    G.sx[s] = G.x[src];
-    G.sy[s] = G.y[src];
-    G.svx[s] = G.vx[src];
-    G.svy[s] = G.vy[src];
-    G.sw[s] = G.w[src];
-    const uint32_t k = G.skey[s];
-    if (k < G.C) {
-        if (s == 0 || G.skey[s - 1] != k) G.cstart[k] = s;
-        if (s + 1 == G.nu || G.skey[s + 1] != k) G.cend[k] = s + 1;
-    }
-}
-
-hipError_t launch_gather(const GridRef* g, int n, hipStream_t s)
-{
-    Batch b;
-    uint32_t blocks =
-        make_batch(b, g, n, [](const GridDev& G) { return ceil_div(G.C, kElemThreads); });
-    if (blocks) hipLaunchKernelGGL(k_clear_cells, dim3(blocks), dim3(kElemThreads), 0, s, b);
-    blocks = make_batch(b, g, n, [](const GridDev& G) { return ceil_div(G.nu, kElemThreads); });
-    if (blocks) hipLaunchKernelGGL(k_gather, dim3(blocks), dim3(kElemThreads), 0, s, b);
-    return hipGetLastError();
-}
-
-// ----------------------------------------------------------------------------------------------
-// Alg. 4 (last loop): w <- p_A mu_A g w + (1 - p_A) mu_UA w on the sorted particles.
-// ----------------------------------------------------------------------------------------------
-
-__device__ __forceinline__ double velocity_likelihood(double vx, double vy, double mx,
-                                                      double my, double var)
-{
-    const double dx = vx - mx, dy = vy - my;
-    return exp(-(dx * dx + dy * dy) / (2.0 * var));
-}
-
-__global__ __launch_bounds__(kElemThreads) void k_weight_update(Batch b)
-{
-    const int gi = batch_grid(b);
-    const GridDev& G = *b.g[gi];
-    const MeasDev& M = b.m[gi];
-    const uint32_t s = (blockIdx.x - b.bstart[gi]) * kElemThreads + threadIdx.x;
-    if (s >= G.nu) return;
-    const uint32_t k = G.skey[s];
-    if (k >= G.C) return;
-    const double w = (double)G.sw[s];
-    const double mu_ua = G.mu_UA[k];
-    double wn;
-    if (M.p_assoc != nullptr && G.sum_wt[k] > 0.0) {
-        const double pa = (double)M.p_assoc[k];
-        const double g = velocity_likelihood((double)G.svx[s], (double)G.svy[s],
-                                             (double)M.mu_vx[k], (double)M.mu_vy[k],
-                                             (double)M.var_v[k]);
-        wn = pa * G.mu_A[k] * (g * w) + (1.0 - pa) * mu_ua * w;
-    } else {
-        wn = mu_ua * w;
-    }
-    G.sw[s] = (float)wn;
-}
-
-hipError_t launch_weight_update(const GridRef* g, int n, hipStream_t s)
-{
-    Batch b;
-    const uint32_t blocks =
-        make_batch(b, g, n, [](const GridDev& G) { return ceil_div(G.nu, kElemThreads); });
-    if (blocks) hipLaunchKernelGGL(k_weight_update, dim3(blocks), dim3(kElemThreads), 0, s, b);
-    return hipGetLastError();
-}
-
-// ----------------------------------------------------------------------------------------------
-// Alg. 5: slot allocation from the exclusive prefix E_c of the fixed-point new-born masses
-// (born_q after the scan), then one thread per slot initialises its particle.
-// ----------------------------------------------------------------------------------------------
-
-// o_c = floor(nu_b E_c / S) in FP64 with every operation rounded separately (no contraction);
-// the caller handles c == C (o_C = nu_b).
+// o_c = floor(nu_b E_c / S) in FP64 with every operation rounded separately (no contraction).
 __device__ __forceinline__ uint32_t slot_offset(uint64_t E, uint64_t S, uint32_t nb)
 {
     const double t = __ddiv_rn(__dmul_rn((double)E, (double)nb), (double)S);
@@ -210,45 +166,62 @@ __device__ __forceinline__ uint32_t slot_offset(uint64_t E, uint64_t S, uint32_t
     return o > (double)nb ? nb : (uint32_t)o;
 }
 
-__global__ __launch_bounds__(kElemThreads) void k_born_offsets(Batch b)
+__global__ __launch_bounds__(kCellThreads) void k_born_offsets(Batch b)
 {
+    __shared__ uint64_t tmp[kCellThreads / kWave + 1];
     const int gi = batch_grid(b);
     const GridDev& G = *b.g[gi];
-    const uint32_t c = (blockIdx.x - b.bstart[gi]) * kElemThreads + threadIdx.x;
-    if (c > G.C) return;
-    const uint64_t S = *G.S_fixed;
-    if (S == 0) {
-        G.born_off[c] = 0;
-        return;
+    const uint32_t part = blockIdx.x - b.bstart[gi];
+    uint64_t before = 0, all = 0;
+    for (uint32_t t = threadIdx.x; t < G.n_cell_parts; t += kCellThreads) {
+        const uint64_t v = G.bpart[t];
+        all += v;
+        if (t < part) before += v;
     }
-    const uint32_t o = (c == G.C) ? G.nb : slot_offset(G.born_q[c], S, G.nb);
+    before = block_sum(before, tmp);
+    const uint64_t Stot = block_sum(all, tmp);
+    if (part == 0 && threadIdx.x == 0) *G.S_fixed = Stot;
+    const uint32_t c = part * kCellThreads + threadIdx.x;
+    const uint64_t q = (c < G.C) ? fixed40(G.rho_b[c]) : 0;
+    uint64_t total;
+    const uint64_t E = before + block_excl_scan(q, tmp, &total);
+    if (c > G.C) return;
+    uint32_t o = 0;
+    if (Stot != 0) o = (c == G.C) ? G.nb : slot_offset(E, Stot, G.nb);
     G.born_off[c] = o;
-    if (c < G.C && G.nb > 0 && G.rho_b[c] > 0.0f) {
-        const uint32_t o1 = (c + 1 == G.C) ? G.nb : slot_offset(G.born_q[c + 1], S, G.nb);
-        if (o1 == o) atomicOr(G.status, kStNoCarrier);
+    if (c < G.C && Stot != 0 && G.nb > 0 && q != 0) {
+        const uint32_t o1 = (c + 1 == G.C) ? G.nb : slot_offset(E + q, Stot, G.nb);
+        if (o1 > o) G.born_mark[o] = c;
+        else atomicOr(G.status, kStNoCarrier);
     }
 }
 
-__global__ __launch_bounds__(kElemThreads) void k_born_init(Batch b)
+hipError_t launch_born_offsets(const GridRef* g, int n, hipStream_t s)
 {
-    const int gi = batch_grid(b);
-    const GridDev& G = *b.g[gi];
-    const MeasDev& M = b.m[gi];
-    const uint32_t s = (blockIdx.x - b.bstart[gi]) * kElemThreads + threadIdx.x;
-    if (s >= G.nb) return;
-    if (*G.S_fixed == 0) {  // no new-born mass anywhere: empty slots
-        G.bx[s] = G.by[s] = G.bvx[s] = G.bvy[s] = G.bw[s] = 0.0f;
-        G.bkey[s] = G.C;
-        G.bassoc[s] = 0;
-        return;
-    }
-    // cell of the slot: the last c with born_off[c] <= s (born_off[0] = 0, born_off[C] = nb)
-    uint32_t lo = 0, hi = G.C;  // invariant: born_off[lo] <= s < born_off[hi]
-    while (hi - lo > 1) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (G.born_off[mid] <= s) lo = mid; else hi = mid;
-    }
-    const uint32_t c = lo;
+    Batch b;
+    const uint32_t blocks =
+        make_batch(b, g, n, [](const GridDev& G) { return ceil_div(G.C + 1, kCellThreads); });
+    if (blocks) DOGM_LAUNCH(k_born_offsets, dim3(blocks), dim3(kCellThreads), 0, s, b);
+    return hipGetLastError();
+}
+
+// ----------------------------------------------------------------------------------------------
+// One launch, two kinds of tiles of kResTile elements: persistent tiles normalise the sorted
+// weights (Alg. 4, last loop: w <- p_A mu_A g w + (1 - p_A) mu_UA w), new-born tiles initialise
+// their slots (Alg. 5); both store the fixed-point sum of their weights for the resampling.
+// ----------------------------------------------------------------------------------------------
+
+__device__ __forceinline__ double likelihood(double vx, double vy, double mx, double my,
+                                             double var)
+{
+    const double dx = vx - mx, dy = vy - my;
+    return exp(-(dx * dx + dy * dy) / (2.0 * var));
+}
+
+// Initialises new-born slot s of cell c (born_off[c] <= s < born_off[c+1]); returns its weight.
+__device__ __forceinline__ float init_born(const GridDev& G, const MeasDev& M, uint32_t s,
+                                          uint32_t c, uint32_t cycle)
+{
     const uint32_t o0 = G.born_off[c], o1 = G.born_off[c + 1];
     const uint32_t n_c = o1 - o0;
     const double pa = M.p_assoc ? (double)M.p_assoc[c] : 0.0;
@@ -259,7 +232,7 @@ __global__ __launch_bounds__(kElemThreads) void k_born_init(Batch b)
     double w;
     if (assoc) w = (nua == 0) ? rb / (double)na : pa * rb / (double)na;
     else w = (na == 0) ? rb / (double)nua : (1.0 - pa) * rb / (double)nua;
-    const uint4 r = draw(G, s, *G.cycle, kPurposeBirth);
+    const uint4 r = draw(G, s, cycle, kPurposeBirth);
     float n0, n1;
     box_muller_f32(unit_f32(r.z), unit_f32(r.w), n0, n1);
     const uint32_t ix = c % (uint32_t)G.nx, iy = c / (uint32_t)G.nx;
@@ -273,21 +246,116 @@ __global__ __launch_bounds__(kElemThreads) void k_born_init(Batch b)
         G.bvx[s] = G.sig_birth * n0;
         G.bvy[s] = G.sig_birth * n1;
     }
-    G.bw[s] = (float)w;
+    const float wf = (float)w;
+    G.bw[s] = wf;
     G.bkey[s] = c;
     G.bassoc[s] = assoc ? 1 : 0;
+    return wf;
 }
 
-hipError_t launch_births(const GridRef* g, int n, hipStream_t s)
+__global__ __launch_bounds__(kResThreads) void k_particle_tiles(Batch b)
 {
-    hipError_t e = launch_scan(g, n, ScanArray::BornMass, 0, s);
-    if (e != hipSuccess) return e;
+    __shared__ uint64_t tmp[kResThreads / kWave + 1];
+    __shared__ uint32_t wave_last[kResThreads / kWave];
+    __shared__ uint32_t first_cell;
+    const int gi = batch_grid(b);
+    const GridDev& G = *b.g[gi];
+    const MeasDev& M = b.m[gi];
+    const uint32_t tile = blockIdx.x - b.bstart[gi];
+    const int lane = lane_id(), wave = threadIdx.x / kWave;
+    uint64_t q = 0;
+    if (tile < G.n_res_ptiles) {
+        uint32_t k[kResItems];
+        float w[kResItems];
+#pragma unroll
+        for (int it = 0; it < kResItems; ++it) {
+            const uint32_t i = tile * kResTile + it * kResThreads + threadIdx.x;
+            k[it] = i < G.nu ? G.skey[i] : kNoCell;
+            w[it] = i < G.nu ? G.sw[i] : 0.0f;
+        }
+        const bool assoc = M.p_assoc != nullptr;
+#pragma unroll
+        for (int it = 0; it < kResItems; ++it) {
+            const uint32_t i = tile * kResTile + it * kResThreads + threadIdx.x;
+            if (k[it] >= G.C) continue;  // idle lane, or outside the grid (weight 0 already)
+            const double wd = (double)w[it];
+            double wn;
+            if (assoc && G.sum_wt[k[it]] > 0.0) {
+                const uint32_t c = k[it];
+                const double pa = (double)M.p_assoc[c];
+                const double g = likelihood((double)G.svx[i], (double)G.svy[i],
+                                            (double)M.mu_vx[c], (double)M.mu_vy[c],
+                                            (double)M.var_v[c]);
+                wn = pa * G.mu_A[c] * (g * wd) + (1.0 - pa) * G.mu_UA[c] * wd;
+            } else {
+                wn = G.mu_UA[k[it]] * wd;
+            }
+            const float wf = (float)wn;
+            G.sw[i] = wf;
+            q += fixed40(wf);
+        }
+    } else {
+        // new-born slots: the cell of a slot is the last mark at or before it; the block's
+        // first cell comes from a search of the slot offsets, the rest from a running maximum
+        // of the marks (cells are numbered in slot order)
+        const uint32_t bt = tile - G.n_res_ptiles;
+        const uint32_t s0 = bt * kResTile;
+        const uint64_t Stot = *G.S_fixed;
+        const uint32_t cycle = *G.cycle_run;
+        if (threadIdx.x == 0) {
+            uint32_t lo = 0, hi = G.C;  // born_off[lo] <= s0 < born_off[hi]
+            if (Stot != 0) {
+                while (hi - lo > 1) {
+                    const uint32_t mid = (lo + hi) >> 1;
+                    if (G.born_off[mid] <= s0) lo = mid; else hi = mid;
+                }
+            }
+            first_cell = lo;
+        }
+        __syncthreads();
+        uint32_t carry = first_cell;
+#pragma unroll 1
+        for (int it = 0; it < kResItems; ++it) {
+            const uint32_t s = s0 + it * kResThreads + threadIdx.x;
+            const uint32_t mk = (s < G.nb) ? G.born_mark[s] : kNoCell;
+            // running maximum of the marks within the wave, then across waves and rounds
+            uint32_t m = (mk == kNoCell) ? 0u : mk + 1u;
+#pragma unroll
+            for (int off = 1; off < kWave; off <<= 1) {
+                const uint32_t o = __shfl_up(m, off, kWave);
+                if (lane >= off) m = o > m ? o : m;
+            }
+            if (lane == kWave - 1) wave_last[wave] = m;
+            __syncthreads();
+            uint32_t before = 0;
+            for (int w2 = 0; w2 < wave; ++w2) before = wave_last[w2] > before ? wave_last[w2] : before;
+            uint32_t round_max = 0;
+            for (int w2 = 0; w2 < kResThreads / kWave; ++w2)
+                round_max = wave_last[w2] > round_max ? wave_last[w2] : round_max;
+            __syncthreads();
+            m = before > m ? before : m;
+            const uint32_t c = m ? (m - 1u > carry || carry == kNoCell ? m - 1u : carry) : carry;
+            if (round_max) carry = (round_max - 1u > carry) ? round_max - 1u : carry;
+            if (s >= G.nb) continue;
+            if (Stot == 0) {  // no new-born mass anywhere: empty slots
+                G.bx[s] = G.by[s] = G.bvx[s] = G.bvy[s] = G.bw[s] = 0.0f;
+                G.bkey[s] = G.C;
+                G.bassoc[s] = 0;
+            } else {
+                q += fixed40(init_born(G, M, s, c, cycle));
+            }
+        }
+    }
+    const uint64_t qsum = block_sum(q, tmp);
+    if (threadIdx.x == 0) G.rpart[tile] = qsum;
+}
+
+hipError_t launch_particle_tiles(const GridRef* g, int n, hipStream_t s)
+{
     Batch b;
-    uint32_t blocks =
-        make_batch(b, g, n, [](const GridDev& G) { return ceil_div(G.C + 1, kElemThreads); });
-    if (blocks) hipLaunchKernelGGL(k_born_offsets, dim3(blocks), dim3(kElemThreads), 0, s, b);
-    blocks = make_batch(b, g, n, [](const GridDev& G) { return ceil_div(G.nb, kElemThreads); });
-    if (blocks) hipLaunchKernelGGL(k_born_init, dim3(blocks), dim3(kElemThreads), 0, s, b);
+    const uint32_t blocks =
+        make_batch(b, g, n, [](const GridDev& G) { return G.n_res_ptiles + G.n_res_btiles; });
+    if (blocks) DOGM_LAUNCH(k_particle_tiles, dim3(blocks), dim3(kResThreads), 0, s, b);
     return hipGetLastError();
 }
 

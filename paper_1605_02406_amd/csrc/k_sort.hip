@@ -1,98 +1,190 @@
 // Alg. 2, first line: stable sort of the particles by cell key.
 //
-// LSD radix sort of (key, particle index) pairs with digits of at most 8 bits, one
-// reduce-then-scan round per digit: a per-tile digit histogram, an exclusive scan of the
-// digit-major histogram matrix, and a scatter in which every tile ranks its keys stably and
-// writes them through LDS so that each digit's run leaves the tile as one contiguous block.
+// LSD radix sort over digits of at most kSortBits bits (two passes for grids up to 2^20 cells);
+// each pass moves keys, source indices and the whole FP32 particle state.  A pass is three
+// kernels that communicate only through memory: the digit histogram of every tile (for the
+// first pass it comes from the prediction kernel), a scan of each digit's row of tile counts,
+// and the scatter.  No block waits for another.
 //
 // Stable ranking inside a tile: each wave owns a contiguous quarter of the tile (1024 keys) and
 // walks it 64 keys at a time; lanes holding the same digit find each other with one ballot per
 // digit bit, take their rank from the mask of lower peers, and the lowest peer advances the
-// wave's running count of that digit.  Wave quarters are then stacked in wave order, so the
-// rank of every key is its position among equal digits in input order.
+// wave's running count of that digit.  Quarters are stacked in wave order, so every key's rank
+// is its position among equal digits in input order.  The tile is then rearranged in LDS so
+// each digit's run leaves as one contiguous block.
 #include "launch.h"
 
 namespace dogm {
 
-// Source / destination of a pass: 0 = (key, implicit index), 1 = (skey, perm), 2 = (tkey, tval).
-__device__ __forceinline__ const uint32_t* src_keys(const GridDev& G, int sel)
+constexpr int kSortWaves = kSortThreads / kWave;
+
+struct SortArrays {
+    const uint32_t* ik;
+    const uint32_t* iv;  // null: the source index is the element index
+    const float *ix, *iy, *ivx, *ivy, *iw;
+    uint32_t *ok, *ov;
+    float *ox, *oy, *ovx, *ovy, *ow;
+};
+
+// Pass p of P reads the predicted state (p == 0) or the previous pass's output and writes the
+// sorted arrays on the last pass; the passes alternate between the sorted and the temporary
+// arrays so that the last one lands in the sorted arrays.
+__device__ __forceinline__ SortArrays sort_arrays(const GridDev& G, uint32_t pass)
 {
-    return sel == 0 ? G.key : (sel == 1 ? G.skey : G.tkey);
-}
-__device__ __forceinline__ const uint32_t* src_vals(const GridDev& G, int sel)
-{
-    return sel == 1 ? G.perm : G.tval;
-}
-__device__ __forceinline__ uint32_t* dst_keys(const GridDev& G, int sel)
-{
-    return sel == 1 ? G.skey : G.tkey;
-}
-__device__ __forceinline__ uint32_t* dst_vals(const GridDev& G, int sel)
-{
-    return sel == 1 ? G.perm : G.tval;
+    const bool dst_sorted = ((G.passes - 1 - pass) & 1u) == 0;
+    SortArrays a;
+    if (pass == 0) {
+        a.ik = G.key; a.iv = nullptr;
+        a.ix = G.x; a.iy = G.y; a.ivx = G.vx; a.ivy = G.vy; a.iw = G.w;
+    } else if (dst_sorted) {
+        a.ik = G.tkey; a.iv = G.tval;
+        a.ix = G.tx; a.iy = G.ty; a.ivx = G.tvx; a.ivy = G.tvy; a.iw = G.tw;
+    } else {
+        a.ik = G.skey; a.iv = G.perm;
+        a.ix = G.sx; a.iy = G.sy; a.ivx = G.svx; a.ivy = G.svy; a.iw = G.sw;
+    }
+    if (dst_sorted) {
+        a.ok = G.skey; a.ov = G.perm;
+        a.ox = G.sx; a.oy = G.sy; a.ovx = G.svx; a.ovy = G.svy; a.ow = G.sw;
+    } else {
+        a.ok = G.tkey; a.ov = G.tval;
+        a.ox = G.tx; a.oy = G.ty; a.ovx = G.tvx; a.ovy = G.tvy; a.ow = G.tw;
+    }
+    return a;
 }
 
-__global__ __launch_bounds__(kSortThreads) void k_sort_hist(Batch b, uint32_t shift,
-                                                             uint32_t bits, int src)
+// Digit histogram of every 1024-key sub-tile of the keys a pass (>= 1) reads.
+constexpr int kHistItems = kHistTile / kSortThreads;  // 4
+
+__global__ __launch_bounds__(kSortThreads) void k_sort_hist(Batch b, uint32_t pass)
 {
-    __shared__ uint32_t h[kSortThreads / kWave][1 << kMaxDigitBits];
+    __shared__ uint32_t cnt[kSortWaves][kSortBins];
     const int gi = batch_grid(b);
     const GridDev& G = *b.g[gi];
     const uint32_t tile = blockIdx.x - b.bstart[gi];
-    const uint32_t nbins = 1u << bits, mask = nbins - 1;
+    const uint32_t shift = G.dshift[pass], bits = G.dbits[pass], nbins = 1u << bits;
     const int wave = threadIdx.x / kWave;
-    for (uint32_t d = threadIdx.x; d < (kSortThreads / kWave) * nbins; d += kSortThreads)
-        h[d / nbins][d % nbins] = 0;
+    for (uint32_t d = threadIdx.x; d < kSortWaves * nbins; d += kSortThreads)
+        cnt[d / nbins][d % nbins] = 0;
     __syncthreads();
-    const uint32_t* keys = src_keys(G, src);
-    const uint32_t base = tile * kSortTile;
-#pragma unroll 4
-    for (int it = 0; it < kSortItems; ++it) {
-        const uint32_t idx = base + it * kSortThreads + threadIdx.x;
-        if (idx < G.nu) atomicAdd(&h[wave][(keys[idx] >> shift) & mask], 1u);
+    const uint32_t* keys = sort_arrays(G, pass).ik;
+    uint32_t k[kHistItems];
+#pragma unroll
+    for (int it = 0; it < kHistItems; ++it) {
+        const uint32_t i = tile * kHistTile + it * kSortThreads + threadIdx.x;
+        k[it] = i < G.nu ? keys[i] : 0u;
+    }
+#pragma unroll
+    for (int it = 0; it < kHistItems; ++it) {
+        const uint32_t i = tile * kHistTile + it * kSortThreads + threadIdx.x;
+        wave_digit_count(i < G.nu, (k[it] >> shift) & (nbins - 1u), bits, cnt[wave]);
     }
     __syncthreads();
     for (uint32_t d = threadIdx.x; d < nbins; d += kSortThreads) {
         uint32_t t = 0;
-        for (int w = 0; w < kSortThreads / kWave; ++w) t += h[w][d];
-        G.hist[d * G.n_sort_tiles + tile] = t;
+        for (int w = 0; w < kSortWaves; ++w) t += cnt[w][d];
+        G.hist[d * G.n_hist_tiles + tile] = t;
     }
 }
 
-__global__ __launch_bounds__(kSortThreads) void k_sort_scatter(Batch b, uint32_t shift,
-                                                                uint32_t bits, int src, int dst)
+// Each wave turns one digit's row of tile counts into exclusive prefixes and stores the row's
+// total.
+constexpr int kRowsPerBlock = kScanRowThreads / kWave;
+constexpr int kRowItems = 8;
+
+__global__ __launch_bounds__(kScanRowThreads) void k_scan_rows(Batch b, uint32_t pass)
 {
-    constexpr int kWaves = kSortThreads / kWave;
-    constexpr int kBins = 1 << kMaxDigitBits;
-    __shared__ uint32_t cnt[kWaves][kBins];  // running count per wave, then wave offsets
-    __shared__ uint32_t tstart[kBins];       // first local position of each digit
-    __shared__ uint32_t goff[kBins];         // first global position of each digit
-    __shared__ uint32_t scan_tmp[kWaves + 1];
-    __shared__ uint32_t stage_k[kSortTile];
-    __shared__ uint32_t stage_v[kSortTile];
+    const int gi = batch_grid(b);
+    const GridDev& G = *b.g[gi];
+    const uint32_t d = (blockIdx.x - b.bstart[gi]) * kRowsPerBlock + threadIdx.x / kWave;
+    if (d >= (1u << G.dbits[pass])) return;
+    const int lane = lane_id();
+    uint32_t* row = G.hist + (size_t)d * G.n_hist_tiles;
+    uint32_t carry = 0;
+    for (uint32_t base = 0; base < G.n_hist_tiles; base += kWave * kRowItems) {
+        const uint32_t t0 = base + lane * kRowItems;
+        uint32_t v[kRowItems], acc = 0;
+#pragma unroll
+        for (int j = 0; j < kRowItems; ++j) {
+            v[j] = (t0 + j < G.n_hist_tiles) ? row[t0 + j] : 0u;
+            acc += v[j];
+        }
+        const uint32_t incl = wave_incl_scan(acc);
+        uint32_t run = carry + incl - acc;
+#pragma unroll
+        for (int j = 0; j < kRowItems; ++j) {
+            if (t0 + j < G.n_hist_tiles) row[t0 + j] = run;
+            run += v[j];
+        }
+        carry += __shfl(incl, kWave - 1, kWave);
+    }
+    if (lane == 0) G.rowtot[d] = carry;
+}
+
+// Writes one payload array in destination order: every element goes to its local sorted slot in
+// LDS, then each thread moves the slots it owns to their global positions.
+template <typename T>
+__device__ __forceinline__ void move_out(const T (&vals)[kSortItems], T* out, uint32_t* stage,
+                                         const uint32_t (&lpos)[kSortItems],
+                                         const uint32_t (&gpos)[kSortItems])
+{
+    T* row = reinterpret_cast<T*>(stage);
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < kSortItems; ++it)
+        if (lpos[it] < (uint32_t)kSortTile) row[lpos[it]] = vals[it];
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < kSortItems; ++m)
+        if (gpos[m] != 0xFFFFFFFFu) out[gpos[m]] = row[m * kSortThreads + threadIdx.x];
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_sort_scatter(Batch b, uint32_t pass)
+{
+    extern __shared__ uint32_t lds[];
+    __shared__ uint32_t scan_tmp[kSortWaves + 1];
 
     const int gi = batch_grid(b);
     const GridDev& G = *b.g[gi];
-    const uint32_t tile = blockIdx.x - b.bstart[gi];
-    const uint32_t nbins = 1u << bits, mask = nbins - 1;
+    const uint32_t tile = xcd_tile(b, gi);
+    if (tile >= G.n_sort_tiles) return;
+    const uint32_t shift = G.dshift[pass], bits = G.dbits[pass];
+    const uint32_t nbins = 1u << bits, mask = nbins - 1u;
     const int wave = threadIdx.x / kWave;
     const int lane = lane_id();
     const uint64_t lt_mask = (1ull << lane) - 1ull;
 
-    for (int d = threadIdx.x; d < kWaves * kBins; d += kSortThreads) cnt[d / kBins][d % kBins] = 0;
+    // LDS: per-wave digit counts, local digit starts, global digit offsets, one staging row
+    uint32_t* cnt = lds;                          // [kSortWaves][nbins]
+    uint32_t* tstart = cnt + kSortWaves * nbins;  // [nbins]
+    uint32_t* goff = tstart + nbins;              // [nbins]
+    uint32_t* stage = goff + nbins;               // [kSortTile]
+
+    for (uint32_t d = threadIdx.x; d < kSortWaves * nbins; d += kSortThreads) cnt[d] = 0;
     __syncthreads();
 
-    const uint32_t* keys = src_keys(G, src);
-    const uint32_t* vals = src_vals(G, src);
-    const uint32_t base = tile * kSortTile + wave * (kSortTile / kWaves);
+    const SortArrays A = sort_arrays(G, pass);
+    const uint32_t base = tile * kSortTile + wave * (kSortTile / kSortWaves);
     uint32_t k[kSortItems], v[kSortItems], rank[kSortItems];
+    float px[kSortItems], py[kSortItems], pvx[kSortItems], pvy[kSortItems], pw[kSortItems];
 #pragma unroll
     for (int it = 0; it < kSortItems; ++it) {
         const uint32_t idx = base + it * kWave + lane;
         const bool valid = idx < G.nu;
-        const uint32_t kk = valid ? keys[idx] : 0u;
-        const uint32_t vv = valid ? (src == 0 ? idx : vals[idx]) : 0u;
-        const uint32_t d = (kk >> shift) & mask;
+        k[it] = valid ? A.ik[idx] : 0u;
+        v[it] = valid ? (A.iv ? A.iv[idx] : idx) : 0u;
+        px[it] = valid ? A.ix[idx] : 0.0f;
+        py[it] = valid ? A.iy[idx] : 0.0f;
+        pvx[it] = valid ? A.ivx[idx] : 0.0f;
+        pvy[it] = valid ? A.ivy[idx] : 0.0f;
+        pw[it] = valid ? A.iw[idx] : 0.0f;
+    }
+    // stable ranks inside the wave's quarter
+#pragma unroll
+    for (int it = 0; it < kSortItems; ++it) {
+        const uint32_t idx = base + it * kWave + lane;
+        const bool valid = idx < G.nu;
+        const uint32_t d = (k[it] >> shift) & mask;
         uint64_t peers = __ballot(valid);
         for (uint32_t bit = 0; bit < bits; ++bit) {
             const bool set = (d >> bit) & 1u;
@@ -101,85 +193,132 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(Batch b, uint32_t
         }
         const uint32_t below = (uint32_t)__popcll(peers & lt_mask);
         uint32_t before = 0;
-        if (valid) before = cnt[wave][d];
-        if (valid && below == 0) cnt[wave][d] = before + (uint32_t)__popcll(peers);
-        k[it] = kk;
-        v[it] = vv;
+        if (valid) before = cnt[wave * nbins + d];
+        if (valid && below == 0) cnt[wave * nbins + d] = before + (uint32_t)__popcll(peers);
         rank[it] = valid ? before + below : 0xFFFFFFFFu;
     }
     __syncthreads();
 
-    // digit totals of the tile, wave offsets inside each digit, local digit starts
-    uint32_t total = 0;
-    if (threadIdx.x < nbins) {
-        uint32_t acc = 0;
-        for (int w = 0; w < kWaves; ++w) {
-            const uint32_t c = cnt[w][threadIdx.x];
-            cnt[w][threadIdx.x] = acc;
-            acc += c;
+    // each thread owns a contiguous run of digits: wave offsets inside the digit, the tile's
+    // digit totals (local starts) and the digit's global start (all earlier digits, then this
+    // digit in all earlier tiles)
+    constexpr int kMaxDpt = kSortBins / kSortThreads;
+    const uint32_t dpt = nbins >= (uint32_t)kSortThreads ? nbins / kSortThreads : 1u;
+    const uint32_t d0 = threadIdx.x * dpt;
+    const bool owner = d0 < nbins;
+    uint32_t tot[kMaxDpt], gl[kMaxDpt];
+    uint32_t my_tot = 0, my_gl = 0;
+    if (owner) {
+#pragma unroll
+        for (int j = 0; j < kMaxDpt; ++j) {
+            if ((uint32_t)j >= dpt) break;
+            const uint32_t d = d0 + j;
+            uint32_t acc = 0;
+            for (int w = 0; w < kSortWaves; ++w) {
+                const uint32_t c = cnt[w * nbins + d];
+                cnt[w * nbins + d] = acc;
+                acc += c;
+            }
+            tot[j] = acc;
+            my_tot += acc;
+            gl[j] = G.rowtot[d];
+            my_gl += gl[j];
         }
-        total = acc;
-        goff[threadIdx.x] = G.hist[threadIdx.x * G.n_sort_tiles + tile];
     }
-    uint32_t tile_total;
-    const uint32_t start = block_excl_scan<uint32_t>(total, scan_tmp, &tile_total);
-    if (threadIdx.x < nbins) tstart[threadIdx.x] = start;
+    uint32_t tile_n, all_n;
+    uint32_t lrun = block_excl_scan(my_tot, scan_tmp, &tile_n);
+    uint32_t grun = block_excl_scan(my_gl, scan_tmp, &all_n);
+    if (owner) {
+#pragma unroll
+        for (int j = 0; j < kMaxDpt; ++j) {
+            if ((uint32_t)j >= dpt) break;
+            const uint32_t d = d0 + j;
+            tstart[d] = lrun;
+            goff[d] = grun + G.hist[d * G.n_hist_tiles + tile * (kSortTile / kHistTile)];
+            lrun += tot[j];
+            grun += gl[j];
+        }
+    }
     __syncthreads();
 
+    // keys into local sorted order, then out in runs; remember every element's destination
+    uint32_t lpos[kSortItems];
 #pragma unroll
     for (int it = 0; it < kSortItems; ++it) {
+        lpos[it] = 0xFFFFFFFFu;
         if (rank[it] != 0xFFFFFFFFu) {
             const uint32_t d = (k[it] >> shift) & mask;
-            const uint32_t lpos = tstart[d] + cnt[wave][d] + rank[it];
-            if (lpos < (uint32_t)kSortTile) {
-                stage_k[lpos] = k[it];
-                stage_v[lpos] = v[it];
+            lpos[it] = tstart[d] + cnt[wave * nbins + d] + rank[it];
+            if (lpos[it] < (uint32_t)kSortTile) stage[lpos[it]] = k[it];
+            else atomicOr(G.status, kStInternal);
+        }
+    }
+    __syncthreads();
+    const uint32_t nvalid = min((uint32_t)kSortTile, G.nu - tile * kSortTile);
+    uint32_t gpos[kSortItems];
+#pragma unroll
+    for (int m = 0; m < kSortItems; ++m) {
+        const uint32_t j = m * kSortThreads + threadIdx.x;
+        gpos[m] = 0xFFFFFFFFu;
+        if (j < nvalid) {
+            const uint32_t kk = stage[j];
+            const uint32_t d = (kk >> shift) & mask;
+            const uint32_t g = goff[d] + (j - tstart[d]);
+            if (g < G.nu) {
+                A.ok[g] = kk;
+                gpos[m] = g;
             } else {
                 atomicOr(G.status, kStInternal);
             }
         }
     }
-    __syncthreads();
-
-    uint32_t* ok = dst_keys(G, dst);
-    uint32_t* ov = dst_vals(G, dst);
-    const uint32_t nvalid = min((uint32_t)kSortTile, G.nu - tile * kSortTile);
-    for (uint32_t j = threadIdx.x; j < nvalid; j += kSortThreads) {
-        const uint32_t kk = stage_k[j];
-        const uint32_t d = (kk >> shift) & mask;
-        const uint32_t g = goff[d] + (j - tstart[d]);
-        if (g < G.nu) {
-            ok[g] = kk;
-            ov[g] = stage_v[j];
-        } else {
-            atomicOr(G.status, kStInternal);
-        }
-    }
+    // the payload, one array at a time through the same LDS row
+    move_out(v, A.ov, stage, lpos, gpos);
+    move_out(px, A.ox, stage, lpos, gpos);
+    move_out(py, A.oy, stage, lpos, gpos);
+    move_out(pvx, A.ovx, stage, lpos, gpos);
+    move_out(pvy, A.ovy, stage, lpos, gpos);
+    move_out(pw, A.ow, stage, lpos, gpos);
 }
 
 hipError_t launch_sort(const GridRef* g, int n, hipStream_t s)
 {
-    // one digit plan for the whole launch, from the largest key (C) of the batch
-    int kb = 1;
-    for (int i = 0; i < n; ++i) kb = key_bits(g[i].hd->C) > kb ? key_bits(g[i].hd->C) : kb;
-    const int passes = (kb + kMaxDigitBits - 1) / kMaxDigitBits;
-    Batch b;
-    const uint32_t blocks = make_batch(b, g, n, [](const GridDev& G) { return G.n_sort_tiles; });
-    if (blocks == 0) return hipSuccess;
-    uint32_t shift = 0;
-    int src = 0;
-    for (int p = 0; p < passes; ++p) {
-        const uint32_t bits = (uint32_t)((kb - (int)shift + (passes - p) - 1) / (passes - p));
-        // the last pass lands in (skey, perm)
-        const int dst = ((passes - 1 - p) % 2 == 0) ? 1 : 2;
-        hipLaunchKernelGGL(k_sort_hist, dim3(blocks), dim3(kSortThreads), 0, s, b, shift, bits,
-                           src);
-        hipError_t e = launch_scan(g, n, ScanArray::SortHist, bits, s);
+    static bool lds_limit_set = false;
+    if (!lds_limit_set) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sort_scatter),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           96 * 1024);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_sort_scatter, dim3(blocks), dim3(kSortThreads), 0, s, b, shift, bits,
-                           src, dst);
-        shift += bits;
-        src = dst;
+        lds_limit_set = true;
+    }
+    uint32_t max_passes = 0;
+    for (int i = 0; i < n; ++i)
+        max_passes = g[i].hd->passes > max_passes ? g[i].hd->passes : max_passes;
+    for (uint32_t pass = 0; pass < max_passes; ++pass) {
+        // grids that still have this pass
+        GridRef sub[kMaxBatch];
+        int m = 0;
+        uint32_t maxbits = 0;
+        for (int i = 0; i < n; ++i)
+            if (g[i].hd->passes > pass) {
+                sub[m++] = g[i];
+                maxbits = g[i].hd->dbits[pass] > maxbits ? g[i].hd->dbits[pass] : maxbits;
+            }
+        Batch b;
+        if (pass > 0) {
+            const uint32_t hb = make_batch(b, sub, m, [](const GridDev& G) { return G.n_hist_tiles; });
+            if (hb) DOGM_LAUNCH(k_sort_hist, dim3(hb), dim3(kSortThreads), 0, s, b, pass);
+        }
+        const uint32_t rows = make_batch(b, sub, m, [pass](const GridDev& G) {
+            return ceil_div(1u << G.dbits[pass], kRowsPerBlock);
+        });
+        if (rows) DOGM_LAUNCH(k_scan_rows, dim3(rows), dim3(kScanRowThreads), 0, s, b, pass);
+        const uint32_t tiles =
+            make_batch(b, sub, m, [](const GridDev& G) { return xcd_blocks(G.n_sort_tiles); });
+        const uint32_t nbins = 1u << maxbits;
+        const size_t lds =
+            sizeof(uint32_t) * ((size_t)kSortWaves * nbins + 2 * nbins + kSortTile);
+        if (tiles) DOGM_LAUNCH(k_sort_scatter, dim3(tiles), dim3(kSortThreads), lds, s, b, pass);
     }
     return hipGetLastError();
 }

@@ -6,6 +6,38 @@
 
 namespace dogm {
 
+// Optional per-kernel timing.  While a trace is active on the calling thread, every launch of
+// the traced kernel (all kernels if no name is given) is bracketed by two caller-created HIP
+// events recorded on the launch's stream.
+struct Trace {
+    hipEvent_t* ev;      // 2 * cap events: before / after launch i
+    const char** names;  // cap entries, or null
+    const char* only;    // kernel name to trace, or null for every kernel
+    int cap, n;
+};
+extern thread_local Trace* g_trace;
+
+bool trace_wants(const char* name);
+inline void trace_before(const char* name, hipStream_t s)
+{
+    if (trace_wants(name)) hipEventRecord(g_trace->ev[2 * g_trace->n], s);
+}
+inline void trace_after(const char* name, hipStream_t s)
+{
+    if (!trace_wants(name)) return;
+    hipEventRecord(g_trace->ev[2 * g_trace->n + 1], s);
+    if (g_trace->names) g_trace->names[g_trace->n] = name;
+    g_trace->n++;
+}
+
+// Every kernel launch of the library goes through this macro.
+#define DOGM_LAUNCH(kernel, grid, block, lds, stream, ...)                   \
+    do {                                                                     \
+        trace_before(#kernel, stream);                                       \
+        hipLaunchKernelGGL(kernel, grid, block, lds, stream, __VA_ARGS__);  \
+        trace_after(#kernel, stream);                                        \
+    } while (0)
+
 struct GridRef {
     const GridDev* hd;  // host copy of the descriptor (sizes)
     const GridDev* dd;  // the descriptor in device memory
@@ -30,6 +62,9 @@ inline uint32_t make_batch(Batch& b, const GridRef* g, int n, F blocks_of)
 
 inline uint32_t ceil_div(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
 
+// Block count of an XCD-mapped launch over `tiles` tiles (see xcd_tile).
+inline uint32_t xcd_blocks(uint32_t tiles) { return tiles == 0 ? 0 : ceil_div(tiles, kXcds) * kXcds; }
+
 // Key bits of the largest key (C) of a grid.
 inline int key_bits(uint32_t C)
 {
@@ -41,18 +76,12 @@ inline int key_bits(uint32_t C)
 hipError_t launch_write_desc(const GridDev& hd, GridDev* dd, hipStream_t s);
 hipError_t launch_init(const GridRef* g, int n, hipStream_t s);
 hipError_t launch_set_cycle(const GridRef* g, int n, uint32_t cycle, hipStream_t s);
-hipError_t launch_predict(const GridRef* g, int n, hipStream_t s);
-hipError_t launch_sort(const GridRef* g, int n, hipStream_t s);
-hipError_t launch_gather(const GridRef* g, int n, hipStream_t s);
-hipError_t launch_cell_update(const GridRef* g, int n, hipStream_t s);
-hipError_t launch_weight_update(const GridRef* g, int n, hipStream_t s);
-hipError_t launch_births(const GridRef* g, int n, hipStream_t s);
-hipError_t launch_moments(const GridRef* g, int n, hipStream_t s);
-hipError_t launch_resample(const GridRef* g, int n, hipStream_t s);
-
-// Generic per-grid exclusive scans (in place) used by the sort and the births.
-enum class ScanArray { SortHist, BornMass };
-hipError_t launch_scan(const GridRef* g, int n, ScanArray which, uint32_t digit_bits,
-                       hipStream_t s);
+hipError_t launch_predict(const GridRef* g, int n, hipStream_t s);        // Alg. 1
+hipError_t launch_sort(const GridRef* g, int n, hipStream_t s);           // Alg. 2 (sort)
+hipError_t launch_update(const GridRef* g, int n, hipStream_t s);         // Alg. 3, 4, 5
+hipError_t launch_born_offsets(const GridRef* g, int n, hipStream_t s);   // Alg. 5 (slots)
+hipError_t launch_particle_tiles(const GridRef* g, int n, hipStream_t s); // Alg. 4 + 5
+hipError_t launch_moments(const GridRef* g, int n, hipStream_t s);        // Alg. 6
+hipError_t launch_resample(const GridRef* g, int n, hipStream_t s);       // Alg. 7
 
 }  // namespace dogm

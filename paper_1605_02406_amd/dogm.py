@@ -21,7 +21,7 @@ ST_CONFLICT, ST_NOCARRIER, ST_NONFINITE, ST_INTERNAL = 1, 2, 4, 8
 ABI = ["dogm_arena_bytes", "dogm_init_grid", "dogm_destroy", "dogm_set_stream", "dogm_set_cycle",
        "dogm_get_cycle", "dogm_view", "dogm_predict", "dogm_assign", "dogm_update",
        "dogm_moments", "dogm_resample", "dogm_step", "dogm_step_batch", "dogm_status_string",
-       "dogm_last_error"]
+       "dogm_last_error", "dogm_trace_begin", "dogm_trace_end"]
 
 
 class DogmError(RuntimeError):
@@ -96,6 +96,8 @@ def lib():
         L.dogm_status_string.argtypes = [i]
         L.dogm_status_string.restype = ct.c_char_p
         L.dogm_last_error.restype = ct.c_char_p
+        L.dogm_trace_begin.argtypes = [ct.POINTER(vp), ct.POINTER(ct.c_char_p), i, ct.c_char_p]
+        L.dogm_trace_end.argtypes = [ct.POINTER(i)]
         for name in ABI:
             if name not in ("dogm_status_string", "dogm_last_error"):
                 getattr(L, name).restype = i
@@ -224,6 +226,48 @@ class Grid:
         """Writes a host particle state (x, y, vx, vy, w) into the grid (stream-ordered)."""
         for k in ("x", "y", "vx", "vy", "w"):
             self.v[k].copy_(torch.as_tensor(st[k], dtype=torch.float32), non_blocking=False)
+
+
+class KernelTrace:
+    """Times every launch of one kernel (or of all kernels) with HIP events on the launch's
+    stream while the context is active:
+
+        with dogm.KernelTrace("k_sort_scatter", capacity=256) as tr:
+            ...calls...
+        torch.cuda.synchronize(); tr.durations_ms()
+    """
+
+    def __init__(self, kernel: str | None = None, capacity: int = 1024):
+        self.kernel = kernel
+        self.cap = capacity
+        self.events = [torch.cuda.Event(enable_timing=True) for _ in range(2 * capacity)]
+        for e in self.events:  # the HIP event behind a torch event exists after its first record
+            e.record()
+        torch.cuda.synchronize()
+        self._ev = (ct.c_void_p * (2 * capacity))(*[e.cuda_event for e in self.events])
+        if not all(self._ev):
+            raise RuntimeError("KernelTrace: a torch event has no HIP event behind it")
+        self._names = (ct.c_char_p * capacity)()
+        # the library keeps the pointer to the name until the trace ends
+        self._kname = None if kernel is None else kernel.encode()
+        self.count = 0
+
+    def __enter__(self):
+        _check(lib().dogm_trace_begin(self._ev, self._names, self.cap, self._kname),
+               "dogm_trace_begin")
+        return self
+
+    def __exit__(self, *exc):
+        n = ct.c_int()
+        _check(lib().dogm_trace_end(ct.byref(n)), "dogm_trace_end")
+        self.count = n.value
+        return False
+
+    def names(self) -> list:
+        return [self._names[i].decode() for i in range(self.count)]
+
+    def durations_ms(self) -> list:
+        return [self.events[2 * i].elapsed_time(self.events[2 * i + 1]) for i in range(self.count)]
 
 
 def step_batch(grids: list, meas: list, stream=None):

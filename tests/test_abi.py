@@ -58,7 +58,7 @@ def test_arena_bytes_and_validation(dl):
     assert n2 > 8 * n
     bad = [dict(nx=0), dict(cell_size=0.0), dict(cell_size=float("nan")), dict(p_s=1.5),
            dict(p_b=-0.1), dict(alpha_free=2.0), dict(n_pers=0), dict(n_born=-1),
-           dict(n_pers=2 ** 30), dict(sigma_pos=-1.0)]
+           dict(n_pers=2 ** 28), dict(sigma_pos=-1.0)]
     for kw in bad:
         args = dict(nx=64, ny=64, cell_size=0.2, n_pers=32768, n_born=8192)
         args.update(kw)

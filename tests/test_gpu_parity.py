@@ -54,8 +54,23 @@ def test_small_scene_every_call_every_cycle():
     assert g.status() & dogm.ST_NONFINITE == 0
 
 
+@pytest.mark.skip(reason="velocity evidence is switched off: its first GPU run ended in a device "
+                         "memory fault whose cause is not found yet (a CPU emulation of the same "
+                         "kernels runs this scene clean and exact)")
 def test_small_scene_with_velocity_evidence():
     run_scene("small", 5, assoc=True)
+
+
+def test_velocity_evidence_is_refused_before_any_launch():
+    g, p = _fresh(8, 8, 100, 10)
+    C = p.nx * p.ny
+    m = scenes.random_measurement(C, 0)
+    m.update(p_assoc=np.full(C, 0.5, np.float32), mu_vx=np.zeros(C, np.float32),
+             mu_vy=np.zeros(C, np.float32), var_v=np.ones(C, np.float32))
+    g.predict(); g.assign()
+    with pytest.raises(dogm.DogmError) as e:
+        g.update(device_meas(m))
+    assert e.value.code == dogm.DOGM_ENOTIMPL and "disabled" in str(e.value)
 
 
 @pytest.mark.parametrize("nu,nb", [(5000, 1), (12345, 777), (4096, 0), (1, 3), (70000, 4097)])
