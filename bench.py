@@ -39,10 +39,11 @@ B_PER_CELL = 92
 CSRC = os.path.join(ROOT, "paper_1605_02406_amd", "csrc")
 KERNEL_SOURCE = {
     "k_predict": "k_particles.hip", "k_sort_hist": "k_sort.hip", "k_scan_rows": "k_sort.hip",
-    "k_sort_scatter": "k_sort.hip", "k_seg_update<false>": "k_cells.hip",
-    "k_seg_update<true>": "k_cells.hip", "k_cells_empty": "k_cells.hip",
-    "k_seg_moments": "k_cells.hip", "k_born_offsets": "k_particles.hip",
-    "k_particle_tiles": "k_particles.hip", "k_resample": "k_resample.hip",
+    "k_sort_scatter": "k_sort.hip", "k_sort_gather": "k_sort.hip", "k_seg_sums<false>": "k_cells.hip",
+    "k_seg_sums<true>": "k_cells.hip", "k_cells<false>": "k_cells.hip",
+    "k_cells<true>": "k_cells.hip", "k_seg_moments": "k_cells.hip",
+    "k_born_offsets": "k_particles.hip", "k_particle_tiles": "k_particles.hip",
+    "k_resample": "k_resample.hip",
 }
 
 
@@ -61,31 +62,35 @@ def sort_plan(C: int, max_bits: int = 11):
 def algorithmic_bytes(kernel: str, nu: int, nb: int, C: int) -> float:
     """Algorithmic bytes of ONE launch of `kernel` on one grid (averaged over the launches of a
     cycle where they differ), from per-unit figures: predict reads x, y, vx, vy, w (20 B) and
-    writes them and the key (24 B); a sort pass reads the key, the source index (from the
-    second pass on) and the five state arrays and writes key, index and state (28 B); the
+    writes them and the key (24 B); a sort pass reads the key and the source index (from the
+    second pass on) and writes both (8 B); the gather reads the permutation and the five
+    state arrays (24 B) and writes the sorted state (20 B); the
     resampling reads every joint weight (4 B), the state of each chosen source (16 B) and
-    writes the 20-byte state of every output; the per-cell pass reads the sorted key, weight
-    and velocity (16 B per particle) and per cell m_F and the measurement (12 B) and writes
-    ranges, sums, masses, normalisers and moments (101 B)."""
+    writes the 20-byte state of every output; the per-cell sums read the sorted key, weight
+    and velocity (16 B per particle) and write ranges and six FP64 sums per cell (56 B); the
+    cell pass reads ranges, sums, m_F and the measurement (68 B) and writes masses,
+    normalisers and moments (61 B) per cell."""
     bits = sort_plan(C)
     if kernel == "k_predict":
         return 44.0 * nu
     if kernel == "k_sort_scatter":
-        per = [(24 if q == 0 else 28) + 28 for q in range(len(bits))]
+        per = [(4 if q == 0 else 8) + 8 for q in range(len(bits))]
         return nu * sum(per) / len(per)
+    if kernel == "k_sort_gather":
+        return 44.0 * nu
     if kernel == "k_sort_hist":
         return 4.0 * nu
     if kernel == "k_scan_rows":
         tiles = -(-nu // 1024)
         return 8.0 * sum(1 << b for b in bits) * tiles / len(bits)
-    if kernel in ("k_seg_update<false>", "k_seg_update<true>"):
-        return 16.0 * nu + (12 + 101) * C
+    if kernel in ("k_seg_sums<false>", "k_seg_sums<true>"):
+        return 16.0 * nu + 56.0 * C
+    if kernel in ("k_cells<false>", "k_cells<true>"):
+        return (68.0 + 61.0) * C
     if kernel == "k_resample":
         return 4.0 * (nu + nb) + 16.0 * nu + 20.0 * nu
     if kernel == "k_particle_tiles":
         return 12.0 * nu + 25.0 * nb
-    if kernel == "k_cells_empty":
-        return 12.0 * C
     if kernel == "k_born_offsets":
         return 8.0 * C
     return float("nan")

@@ -104,7 +104,7 @@ typedef struct dogm_views {
     uint32_t* perm;       /* sorted position -> index in x..w (nu)                          */
     /* cells (C each unless noted) */
     uint32_t *cell_start, *cell_end; /* particle range [start, end) of each cell in sorted
-                                         order, recorded by update; empty: start == end  */
+                                         order (after assign); empty cells: start == end */
     double* sum_w;        /* sum of predicted persistent weights (FP64; 0 for empty cells) */
     float *m_pO, *m_pF;   /* predicted BBA                                                  */
     float *m_O, *m_F;     /* posterior BBA; m_F is also the state carried to the next cycle  */
@@ -158,9 +158,8 @@ int dogm_view(const dogm_grid* grid, dogm_views* views);
  * (index, cycle, 1, grid_id); writes the cell key (C and w' = 0 outside the grid). */
 int dogm_predict(dogm_grid* grid);
 
-/* Alg. 2: stable sort of the particles by cell key into sx..sw / skey / perm.  The particle
- * range of every cell (cell_start, cell_end) is recorded by the per-cell pass of dogm_update,
- * which walks the sorted keys anyway. */
+/* Alg. 2: stable sort of the particles by cell key into sx..sw / skey / perm, and the
+ * particle range of every cell (cell_start, cell_end; empty cells have start == end). */
 int dogm_assign(dogm_grid* grid);
 
 /* Alg. 3, 4 and 5 in the paper's order:
@@ -171,8 +170,8 @@ int dogm_assign(dogm_grid* grid);
  *  - new-born particles: nu_b slots allocated in proportion to rho_b, split into associated /
  *    unassociated sets, uniform position in the cell, velocity from p(x|z) or N(0, sigma_B^2),
  *    weights of eqs. (weights_associated), (weights_unassociated).
- * Also records cell_start / cell_end.  Without velocity evidence (p_assoc NULL) the updated
- * weights are mu_UA w, so the same pass also writes the velocity moments of Alg. 6.
+ * Without velocity evidence (p_assoc NULL) the updated weights are mu_UA w, so the update
+ * also writes the velocity moments of Alg. 6.
  * `meas` is a host struct of device pointers (see dogm_meas).  DOGM_EINVAL if m_occ/m_free is
  * NULL or p_assoc is given without mu_vx/mu_vy/var_v. */
 int dogm_update(dogm_grid* grid, const dogm_meas* meas);

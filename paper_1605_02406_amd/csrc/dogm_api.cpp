@@ -113,14 +113,14 @@ GridDev describe(const dogm_params* p, char* base, size_t* bytes)
     d.n_cell_parts = ceil_div(C, kCellThreads);
     d.n_res_ptiles = ceil_div(nu, kResTile);
     d.n_res_btiles = ceil_div(nb, kResTile);
+    d.n_born_parts = ceil_div(nb, kBornTile);
 
     Layout L;
     L.take(sizeof(GridDev));
     const size_t f_nu = 4ull * nu, f_nb = 4ull * nb, f_c = 4ull * C, d_c = 8ull * C;
-    float** pf_nu[] = {&d.x, &d.y, &d.vx, &d.vy, &d.w, &d.sx, &d.sy, &d.svx, &d.svy, &d.sw,
-                       &d.tx, &d.ty, &d.tvx, &d.tvy, &d.tw};
-    size_t o_pf_nu[15];
-    for (int i = 0; i < 15; ++i) o_pf_nu[i] = L.take(f_nu);
+    float** pf_nu[] = {&d.x, &d.y, &d.vx, &d.vy, &d.w, &d.sx, &d.sy, &d.svx, &d.svy, &d.sw};
+    size_t o_pf_nu[10];
+    for (int i = 0; i < 10; ++i) o_pf_nu[i] = L.take(f_nu);
     uint32_t** pu_nu[] = {&d.key, &d.skey, &d.perm, &d.tkey, &d.tval};
     size_t o_pu_nu[5];
     for (int i = 0; i < 5; ++i) o_pu_nu[i] = L.take(f_nu);
@@ -130,6 +130,7 @@ GridDev describe(const dogm_params* p, char* base, size_t* bytes)
     double** pd_c[] = {&d.sum_w, &d.sum_wt, &d.mu_A, &d.mu_UA};
     size_t o_pd_c[4];
     for (int i = 0; i < 4; ++i) o_pd_c[i] = L.take(d_c);
+    const size_t o_msum = L.take(5 * d_c);
     float** pf_c[] = {&d.m_pO, &d.m_pF, &d.m_O, &d.m_F, &d.rho_b, &d.rho_p, &d.pign,
                       &d.mean_x, &d.mean_y, &d.var_x, &d.var_y, &d.cov_xy};
     size_t o_pf_c[12];
@@ -143,16 +144,18 @@ GridDev describe(const dogm_params* p, char* base, size_t* bytes)
     const size_t o_rowtot = L.take(4ull * kSortBins);
     const size_t o_bpart = L.take(8ull * d.n_cell_parts);
     const size_t o_mark = L.take(f_nb);
-    const size_t o_rpart = L.take(8ull * (d.n_res_ptiles + d.n_res_btiles));
+    const size_t o_rpart = L.take(8ull * (d.n_res_ptiles + d.n_born_parts));
+    const size_t o_tfirst = L.take(4ull * d.n_born_parts);
     const size_t o_cyc = L.take(4), o_cycr = L.take(4), o_st = L.take(4), o_W = L.take(8),
                  o_S = L.take(8);
     *bytes = L.total;
     if (!base) return d;
 
-    for (int i = 0; i < 15; ++i) *pf_nu[i] = at<float>(base, o_pf_nu[i]);
+    for (int i = 0; i < 10; ++i) *pf_nu[i] = at<float>(base, o_pf_nu[i]);
     for (int i = 0; i < 5; ++i) *pu_nu[i] = at<uint32_t>(base, o_pu_nu[i]);
     for (int i = 0; i < 2; ++i) *pu_c[i] = at<uint32_t>(base, o_pu_c[i]);
     for (int i = 0; i < 4; ++i) *pd_c[i] = at<double>(base, o_pd_c[i]);
+    d.msum = at<double>(base, o_msum);
     for (int i = 0; i < 12; ++i) *pf_c[i] = at<float>(base, o_pf_c[i]);
     d.born_off = at<uint32_t>(base, o_boff);
     d.mflag = at<uint8_t>(base, o_mfl);
@@ -164,6 +167,7 @@ GridDev describe(const dogm_params* p, char* base, size_t* bytes)
     d.bpart = at<uint64_t>(base, o_bpart);
     d.rpart = at<uint64_t>(base, o_rpart);
     d.born_mark = at<uint32_t>(base, o_mark);
+    d.tile_first = at<uint32_t>(base, o_tfirst);
     d.cycle = at<uint32_t>(base, o_cyc);
     d.cycle_run = at<uint32_t>(base, o_cycr);
     d.status = at<uint32_t>(base, o_st);

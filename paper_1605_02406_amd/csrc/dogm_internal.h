@@ -33,7 +33,8 @@ constexpr int kSortBits = 11;
 constexpr int kSortBins = 1 << kSortBits;  // 2048
 constexpr int kMaxPasses = 3;              // keys < 2^27 (C < 2^26 plus the outside key)
 constexpr int kScanRowThreads = 256;       // one block scans a few digit rows of the histogram
-constexpr int kHistTile = 1024;            // keys per digit-histogram sub-tile
+constexpr int kHistTile = kSortTile;       // keys per digit-histogram tile
+constexpr int kHistThreads = 1024;         // histogram blocks: kHistTile / kHistThreads keys each
 constexpr uint32_t kNoCell = 0xFFFFFFFFu;
 
 // Cells: one per thread, partial sums per block of kCellThreads cells.
@@ -48,10 +49,15 @@ constexpr int kSegItems = 8;
 constexpr int kSegRange = kWave * kSegItems;                           // 512
 constexpr int kSegBlockParticles = (kSegThreads / kWave) * kSegRange;  // 2048
 
+// New-born slots are initialised in tiles of kBornTile slots (one per thread); their fixed-point
+// weight sums follow the persistent tiles' sums in the resampling's list of partial sums.
+constexpr int kBornTile = 256;
+
 // Resampling: tiles of persistent particles, then tiles of new-born slots.
 constexpr int kResThreads = 256;
 constexpr int kResItems = 8;
 constexpr int kResTile = kResThreads * kResItems;  // 2048
+static_assert(kResTile % kBornTile == 0, "a resampling tile covers whole new-born tiles");
 
 constexpr int kElemThreads = 256;  // element-wise kernels
 
@@ -64,19 +70,19 @@ struct GridDev {
     // sort plan (from the largest key, C) and tilings
     uint32_t passes;
     uint32_t dshift[kMaxPasses], dbits[kMaxPasses];
-    uint32_t n_sort_tiles, n_hist_tiles, n_cell_parts, n_res_ptiles, n_res_btiles;
+    uint32_t n_sort_tiles, n_hist_tiles, n_cell_parts, n_res_ptiles, n_res_btiles, n_born_parts;
     // persistent particles (start of a cycle / after resampling) and their cell keys
     float *x, *y, *vx, *vy, *w;
     uint32_t* key;
     // particles sorted by cell
     float *sx, *sy, *svx, *svy, *sw;
     uint32_t *skey, *perm;
-    // ping-pong partner of the sorted arrays during the sort
-    float *tx, *ty, *tvx, *tvy, *tw;
+    // ping-pong partner of the sorted keys and permutation during the sort
     uint32_t *tkey, *tval;
     // cells
     uint32_t *cstart, *cend;
     double *sum_w, *sum_wt;
+    double* msum;  // [5][C]: sums of w vx, w vy, w vx^2, w vy^2, w vx vy per cell
     float *m_pO, *m_pF, *m_O, *m_F, *rho_b, *rho_p, *pign;
     double *mu_A, *mu_UA;
     uint32_t* born_off;
@@ -88,11 +94,12 @@ struct GridDev {
     uint8_t* bassoc;
     // per-cycle scratch: digit histograms of 1024-key sub-tiles (digit-major,
     // [kSortBins][n_hist_tiles]) with their row totals, fixed-point partial sums of new-born
-    // masses (per 256 cells) and joint weights (per resampling tile), and the first slot of
-    // every cell with births (its cell id, kNoCell elsewhere)
+    // masses (per 256 cells) and of joint weights (per persistent resampling tile, then per
+    // new-born tile), the first slot of every cell with births (its cell id, kNoCell
+    // elsewhere) and the cell of the first slot of every new-born tile
     uint32_t *hist, *rowtot;
     uint64_t *bpart, *rpart;
-    uint32_t* born_mark;
+    uint32_t *born_mark, *tile_first;
     // device scalars: the cycle to run next (advanced by the resampling) and the cycle being
     // run (set by the prediction); every writer of either stores one and the same value
     uint32_t* cycle;
@@ -147,8 +154,10 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 ctr, uint32_t key_lo, uint3
     for (int round = 0; round < 10; ++round) {
         const uint32_t ka = key_lo + W0 * (uint32_t)round;
         const uint32_t kb = key_hi + W1 * (uint32_t)round;
-        const uint32_t hi_a = __umulhi(M0, a), lo_a = M0 * a;
-        const uint32_t hi_c = __umulhi(M1, c), lo_c = M1 * c;
+        // each product as one 32 x 32 -> 64-bit multiply (both halves from one instruction)
+        const uint64_t pa = (uint64_t)M0 * a, pc = (uint64_t)M1 * c;
+        const uint32_t hi_a = (uint32_t)(pa >> 32), lo_a = (uint32_t)pa;
+        const uint32_t hi_c = (uint32_t)(pc >> 32), lo_c = (uint32_t)pc;
         a = hi_c ^ b ^ ka;
         b = lo_c;
         c = hi_a ^ d ^ kb;
@@ -169,13 +178,16 @@ __device__ __forceinline__ float unit_f32(uint32_t bits)
     return ((float)(bits >> 9) + 0.5f) * 0x1p-23f;
 }
 
+// Box-Muller on the transcendental units: v_log_f32 is log2, v_sqrt_f32 the square root and
+// v_sin_f32 / v_cos_f32 take their argument in revolutions, so sin(2 pi u2) is one instruction.
+// Each is accurate to a few units in the last place, far inside the position and velocity
+// tolerances; the cell key is decided afterwards from the stored FP32 position.
 __device__ __forceinline__ void box_muller_f32(float u1, float u2, float& n1, float& n2)
 {
-    const float radius = sqrtf(-2.0f * logf(u1));
-    float s, c;
-    sincospif(2.0f * u2, &s, &c);
-    n1 = radius * c;
-    n2 = radius * s;
+    const float ln_u1 = __builtin_amdgcn_logf(u1) * 0.693147180559945309f;  // ln 2
+    const float radius = __builtin_amdgcn_sqrtf(-2.0f * ln_u1);
+    n1 = radius * __builtin_amdgcn_cosf(u2);
+    n2 = radius * __builtin_amdgcn_sinf(u2);
 }
 
 // Cell of an FP32 position: one correctly rounded FP32 division per axis, C outside the grid.
@@ -230,8 +242,9 @@ __device__ __forceinline__ int32_t wave_max(int32_t v)
     return v;
 }
 
-// Adds this wave's count of every digit to cnt[d]: lanes holding the same digit find each other
-// with one ballot per digit bit, and the lowest of them adds their number.
+// Adds this wave's count of every digit to the block's LDS histogram cnt[d]: lanes holding the
+// same digit find each other with one ballot per digit bit, and the lowest of them adds their
+// number with one LDS atomic.
 __device__ __forceinline__ void wave_digit_count(bool valid, uint32_t d, uint32_t bits,
                                                  uint32_t* cnt)
 {
@@ -242,7 +255,7 @@ __device__ __forceinline__ void wave_digit_count(bool valid, uint32_t d, uint32_
         peers &= set ? bb : ~bb;
     }
     const uint64_t lt = (1ull << lane_id()) - 1ull;
-    if (valid && (peers & lt) == 0) cnt[d] += (uint32_t)__popcll(peers);
+    if (valid && (peers & lt) == 0) atomicAdd(&cnt[d], (uint32_t)__popcll(peers));
 }
 
 // Block-wide exclusive scan of one value per thread (blockDim.x a multiple of 64).  `lds` must

@@ -2,42 +2,33 @@
 // Dempster-Shafer cell update with the new-born split (Alg. 3), the normalisation components of
 // the persistent update (Alg. 4) and the velocity moments (Alg. 6).
 //
-// Per-cell sums are segmented reductions over the sorted particles instead of the paper's
-// prefix-sum differences (a global FP32 prefix loses the digits of late cells).  Each wave owns
-// 64 * kSegItems particles and every cell whose first particle lies there, reading on past its
-// range to finish its last cell.  Within a chunk each lane adds up kSegItems consecutive
-// particles, closing the cells that end inside it, and one segmented scan across the lanes joins
-// the cells that span lanes; the running sum of a cell still open at the end of the chunk is
-// carried into the next one.  Accumulators are FP64 and the summation order depends only on the
-// data, never on the launch or the batch.  The same pass records where each cell's particles
-// start and end.
+// Two passes.  The first is particle-parallel: per-cell sums are segmented reductions over the
+// sorted particles instead of the paper's prefix-sum differences (a global FP32 prefix loses the
+// digits of late cells).  Each wave owns 64 * kSegItems particles and every cell whose first
+// particle lies there, reading on past its range to finish its last cell.  Within a chunk each
+// lane adds up kSegItems consecutive particles, closing the cells that end inside it, and one
+// segmented scan across the lanes joins the cells that span lanes; the running sum of a cell
+// still open at the end of the chunk is carried into the next one.  Accumulators are FP64 and
+// the summation order depends only on the data, never on the launch or the batch.  A closed
+// cell only stores its sums.  The second pass is cell-parallel: one thread per cell
+// (empty or not) runs the update with every lane of the wave busy.
 //
 // Without velocity evidence (p_A = 0) the updated persistent weights are w' = mu_UA w, so the
 // velocity moments of the updated particles, normalised by rho_p = mu_UA sum w, equal the plain
-// weighted moments of the predicted ones: the same pass that sums the weights also sums w v,
-// w v^2 and w vx vy, and the cell's last lane writes masses and moments together.  With velocity
-// evidence the moments need the updated weights and take a pass of their own.
+// weighted moments of the predicted ones: the first pass also sums w v, w v^2 and w vx vy, and
+// the second writes masses and moments together.  With velocity evidence the moments need the
+// updated weights and take a pass of their own.
 #include "launch.h"
 
 namespace dogm {
 
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 
-// First index in [from, to) whose key differs from `key` (to if none), found 64 keys at a time.
-__device__ __forceinline__ uint32_t first_other(const uint32_t* skey, uint32_t from, uint32_t to,
-                                                uint32_t key)
-{
-    for (uint32_t base = from; base < to; base += kWave) {
-        const uint32_t i = base + lane_id();
-        const uint64_t m = __ballot(i < to && skey[i] != key);
-        if (m) return base + (uint32_t)(__ffsll((unsigned long long)m) - 1);
-    }
-    return to;
-}
-
 // One wave's share of a segmented reduction with NV FP64 sums per particle.
 //   val(k, w, vx, vy, v): v[0..NV) of a particle of cell k with weight w and velocity (vx, vy)
 //   emit(k, v)          : the complete sums of cell k (called once per cell, by one lane)
+// The cell ranges recorded by the sort decide where the wave starts (after the cell that began
+// before its share) and ends (with the cell that holds its last particle).
 template <int NV, typename Val, typename Emit>
 __device__ __forceinline__ void seg_reduce(const GridDev& G, uint32_t wave_index, Val val,
                                            Emit emit)
@@ -49,16 +40,15 @@ __device__ __forceinline__ void seg_reduce(const GridDev& G, uint32_t wave_index
     const uint32_t b = min(a + (uint32_t)kSegRange, n);
     const uint32_t ka = G.skey[a];
     if (ka >= C) return;  // only particles outside the grid from here on
-    // skip the cell that began before a (an earlier wave owns it); finish the cell holding b - 1
-    const uint32_t p0 = (a > 0 && G.skey[a - 1] == ka) ? first_other(G.skey, a, b, ka) : a;
+    const uint32_t p0 = (a > 0 && G.skey[a - 1] == ka) ? G.cend[ka] : a;
     if (p0 >= b) return;
     const uint32_t kl = G.skey[b - 1];
-    const uint32_t pend = (kl < C && b < n) ? first_other(G.skey, b, n, kl) : b;
+    const uint32_t pend = kl < C ? G.cend[kl] : b;
 
     double carry[NV];
 #pragma unroll
     for (int j = 0; j < NV; ++j) carry[j] = 0.0;
-    uint32_t carry_key = kNone, prev_chunk_tail = kNone;
+    uint32_t carry_key = kNone;
 
     for (uint32_t base = p0; base < pend; base += kSegRange) {
         // this lane's run of kSegItems particles: loads first
@@ -89,8 +79,6 @@ __device__ __forceinline__ void seg_reduce(const GridDev& G, uint32_t wave_index
         for (int it = 0; it < kSegItems; ++it) {
             const uint32_t k = key[it];
             if (it > 0 && k != cur) {  // the cell `cur` ends inside this lane
-                if (cur != kNone) G.cend[cur] = i0 + it;
-                if (k != kNone) G.cstart[k] = i0 + it;
                 if (!multi) {
 #pragma unroll
                     for (int j = 0; j < NV; ++j) head[j] = acc[j];
@@ -110,10 +98,6 @@ __device__ __forceinline__ void seg_reduce(const GridDev& G, uint32_t wave_index
             }
         }
         const uint32_t prev_tail = __shfl_up(cur, 1, kWave);
-        // a cell starts at this lane's first particle unless the previous particle is its own
-        const uint32_t before_first =
-            lane == 0 ? (base == p0 ? kNone : prev_chunk_tail) : prev_tail;
-        if (first != kNone && before_first != first) G.cstart[first] = i0;
         // the cell carried in from the previous chunk continues in lane 0
         if (lane == 0 && first != kNone && first == carry_key) {
             if (multi) {
@@ -158,14 +142,10 @@ __device__ __forceinline__ void seg_reduce(const GridDev& G, uint32_t wave_index
             next_first = (inext < pend) ? G.skey[inext] : kNone;
             if (next_first >= C) next_first = kNone;
         }
-        if (cur != kNone && next_first != cur) {
-            G.cend[cur] = i0 + kSegItems;
-            emit(cur, run);
-        }
+        if (cur != kNone && next_first != cur) emit(cur, run);
         const uint32_t t63 = __shfl(cur, kWave - 1, kWave);
         const uint32_t n63 = __shfl(next_first, kWave - 1, kWave);
         carry_key = (t63 != kNone && n63 == t63) ? t63 : kNone;
-        prev_chunk_tail = t63;
 #pragma unroll
         for (int j = 0; j < NV; ++j) carry[j] = __shfl(run[j], kWave - 1, kWave);
     }
@@ -182,9 +162,9 @@ __device__ __forceinline__ double likelihood(double vx, double vy, double mx, do
 // combination with the measurement (eq. (DS_comb)), new-born split (eqs.
 // (DS_resulting_masses1/2), new-born mass only where m_z(O) > 0) and the normalisation
 // components (eqs. (DSnormalizationfactor), (DSnormalizationfactor2)).  s = sum of predicted
-// weights, st = sum of g w.  Returns rho_p (also stored).
+// weights, st = sum of g w.  Returns rho_p; *rb_out gets the stored rho_b.
 __device__ __forceinline__ double cell_update(const GridDev& G, const MeasDev& M, uint32_t c,
-                                              double s, double st)
+                                              double s, double st, float* rb_out)
 {
     const double po = s < 1.0 ? s : 1.0;
     const double pf_cand = (double)G.alpha * (double)G.m_F[c];
@@ -212,8 +192,6 @@ __device__ __forceinline__ double cell_update(const GridDev& G, const MeasDev& M
     }
     const double rp = o - rb;
     if (!isfinite(o) || !isfinite(f) || !isfinite(s)) st_bits |= kStNonFinite;
-    G.sum_w[c] = s;
-    G.sum_wt[c] = st;
     G.m_pO[c] = (float)po;
     G.m_pF[c] = (float)pf;
     G.m_O[c] = (float)o;
@@ -224,11 +202,12 @@ __device__ __forceinline__ double cell_update(const GridDev& G, const MeasDev& M
     G.mu_UA[c] = s > 0.0 ? rp / s : 0.0;
     G.mu_A[c] = st > 0.0 ? rp / st : 0.0;
     if (st_bits) atomicOr(G.status, st_bits);
+    *rb_out = (float)rb;
     return rp;
 }
 
 // Moments are defined where the stored rho_p is positive and the cell holds particles (the
-// caller knows the latter); sums over weights that are all zero give zero moments.
+// caller decides); sums over weights that are all zero give zero moments.
 __device__ __forceinline__ void write_moments(const GridDev& G, uint32_t c, bool defined,
                                               double norm, double sx, double sy, double sxx,
                                               double syy, double sxy)
@@ -238,21 +217,23 @@ __device__ __forceinline__ void write_moments(const GridDev& G, uint32_t c, bool
         G.mflag[c] = defined ? 1 : 0;
         return;
     }
-    const double mx = sx / norm, my = sy / norm;
+    const double inv = 1.0 / norm;
+    const double mx = sx * inv, my = sy * inv;
     G.mean_x[c] = (float)mx;
     G.mean_y[c] = (float)my;
-    G.var_x[c] = (float)(sxx / norm - mx * mx);
-    G.var_y[c] = (float)(syy / norm - my * my);
-    G.cov_xy[c] = (float)(sxy / norm - mx * my);
+    G.var_x[c] = (float)(sxx * inv - mx * mx);
+    G.var_y[c] = (float)(syy * inv - my * my);
+    G.cov_xy[c] = (float)(sxy * inv - mx * my);
     G.mflag[c] = 1;
 }
 
 // ----------------------------------------------------------------------------------------------
-// Alg. 3 + 4 (+ 6 without velocity evidence) on the cells that hold particles.
+// Pass 1: per-cell sums of the cells that hold particles (Alg. 3 sum, Alg. 4 sum of g w, Alg. 6
+// sums without velocity evidence).
 // ----------------------------------------------------------------------------------------------
 
 template <bool kAssoc>
-__global__ __launch_bounds__(kSegThreads) void k_seg_update(Batch b)
+__global__ __launch_bounds__(kSegThreads) void k_seg_sums(Batch b)
 {
     const int gi = batch_grid(b);
     const GridDev& G = *b.g[gi];
@@ -267,7 +248,10 @@ __global__ __launch_bounds__(kSegThreads) void k_seg_update(Batch b)
                 v[1] = likelihood((double)vx, (double)vy, (double)M.mu_vx[k],
                                   (double)M.mu_vy[k], (double)M.var_v[k]) * (double)w;
             },
-            [&](uint32_t k, const double* v) { cell_update(G, M, k, v[0], v[1]); });
+            [&](uint32_t k, const double* v) {
+                G.sum_w[k] = v[0];
+                G.sum_wt[k] = v[1];
+            });
     } else {
         seg_reduce<6>(
             G, wave,
@@ -281,17 +265,20 @@ __global__ __launch_bounds__(kSegThreads) void k_seg_update(Batch b)
                 v[5] = wd * x * y;
             },
             [&](uint32_t k, const double* v) {
-                const double rp = cell_update(G, M, k, v[0], 0.0);
-                // moments of the updated weights mu_UA w, normalised by rho_p = mu_UA sum w
-                write_moments(G, k, (float)rp > 0.0f, v[0], v[1], v[2], v[3], v[4], v[5]);
+                G.sum_w[k] = v[0];
+#pragma unroll
+                for (int j = 0; j < 5; ++j) G.msum[(size_t)j * G.C + k] = v[1 + j];
             });
     }
 }
 
-// Empty cells: no predicted mass, the same update with sum w = 0, moments undefined.  Every
-// block also stores the fixed-point new-born mass of its cells (all of them; the non-empty ones
-// were updated by the previous kernel).
-__global__ __launch_bounds__(kCellThreads) void k_cells_empty(Batch b)
+// ----------------------------------------------------------------------------------------------
+// Pass 2: every cell, one per thread: Alg. 3 + the normalisers of Alg. 4 (+ Alg. 6 without
+// velocity evidence); each block also stores the fixed-point new-born mass of its cells.
+// ----------------------------------------------------------------------------------------------
+
+template <bool kAssoc>
+__global__ __launch_bounds__(kCellThreads) void k_cells(Batch b)
 {
     __shared__ uint64_t tmp[kCellThreads / kWave + 1];
     const int gi = batch_grid(b);
@@ -301,11 +288,27 @@ __global__ __launch_bounds__(kCellThreads) void k_cells_empty(Batch b)
     const uint32_t c = part * kCellThreads + threadIdx.x;
     uint64_t q = 0;
     if (c < G.C) {
-        if (G.cend[c] == G.cstart[c]) {
-            cell_update(G, M, c, 0.0, 0.0);
-            write_moments(G, c, false, 0, 0, 0, 0, 0, 0);
+        const bool has = G.cend[c] != G.cstart[c];
+        double s = 0.0, st = 0.0, m[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+        if (has) {
+            s = G.sum_w[c];
+            if (kAssoc) {
+                st = G.sum_wt[c];
+            } else {
+#pragma unroll
+                for (int j = 0; j < 5; ++j) m[j] = G.msum[(size_t)j * G.C + c];
+            }
+        } else {
+            G.sum_w[c] = 0.0;
+            if (kAssoc) G.sum_wt[c] = 0.0;
         }
-        q = fixed40(G.rho_b[c]);
+        float rb;
+        const double rp = cell_update(G, M, c, s, st, &rb);
+        // moments of the updated weights mu_UA w, normalised by rho_p = mu_UA sum w; with
+        // velocity evidence those of cells with particles come from their own pass
+        if (!kAssoc) write_moments(G, c, has && (float)rp > 0.0f, s, m[0], m[1], m[2], m[3], m[4]);
+        else if (!has) write_moments(G, c, false, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0);
+        q = fixed40(rb);
     }
     const uint64_t qsum = block_sum(q, tmp);
     if (threadIdx.x == 0) G.bpart[part] = qsum;
@@ -325,12 +328,17 @@ hipError_t launch_update(const GridRef* g, int n, hipStream_t s)
     });
     if (blocks) {
         if (any_assoc)
-            DOGM_LAUNCH(k_seg_update<true>, dim3(blocks), dim3(kSegThreads), 0, s, b);
+            DOGM_LAUNCH(k_seg_sums<true>, dim3(blocks), dim3(kSegThreads), 0, s, b);
         else
-            DOGM_LAUNCH(k_seg_update<false>, dim3(blocks), dim3(kSegThreads), 0, s, b);
+            DOGM_LAUNCH(k_seg_sums<false>, dim3(blocks), dim3(kSegThreads), 0, s, b);
     }
     blocks = make_batch(b, g, n, [](const GridDev& G) { return G.n_cell_parts; });
-    if (blocks) DOGM_LAUNCH(k_cells_empty, dim3(blocks), dim3(kCellThreads), 0, s, b);
+    if (blocks) {
+        if (any_assoc)
+            DOGM_LAUNCH(k_cells<true>, dim3(blocks), dim3(kCellThreads), 0, s, b);
+        else
+            DOGM_LAUNCH(k_cells<false>, dim3(blocks), dim3(kCellThreads), 0, s, b);
+    }
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = launch_born_offsets(g, n, s);
     if (e == hipSuccess) e = launch_particle_tiles(g, n, s);

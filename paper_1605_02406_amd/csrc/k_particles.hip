@@ -70,26 +70,26 @@ hipError_t launch_set_cycle(const GridRef* g, int n, uint32_t cycle, hipStream_t
 
 // ----------------------------------------------------------------------------------------------
 // Alg. 1: constant-velocity prediction with Philox noise, persistence, cell key.  One block per
-// 1024 particles: it also stores its digit histogram for the sort's first pass.  The blocks
+// sort tile (kHistTile particles): it also stores the tile's digit histogram for the sort's first
+// pass.  The blocks
 // also clear what later kernels fill in sparsely (cell ranges, first-slot marks) and record the
 // cycle being run.
 // ----------------------------------------------------------------------------------------------
 
-constexpr int kPredItems = kHistTile / kElemThreads;  // 4
+constexpr int kPredItems = kHistTile / kHistThreads;  // 4
 
-__global__ __launch_bounds__(kElemThreads) void k_predict(Batch b)
+__global__ __launch_bounds__(kHistThreads) void k_predict(Batch b)
 {
-    __shared__ uint32_t cnt[kElemThreads / kWave][kSortBins];
+    __shared__ uint32_t cnt[kSortBins];
     const int gi = batch_grid(b);
     const GridDev& G = *b.g[gi];
     const uint32_t tile = xcd_tile(b, gi);
     if (tile >= G.n_hist_tiles) return;
     const uint32_t cycle = *G.cycle;
     const uint32_t shift = G.dshift[0], bits = G.dbits[0], nbins = 1u << bits;
-    const int wave = threadIdx.x / kWave;
 
-    const uint32_t nthreads = G.n_hist_tiles * kElemThreads;
-    const uint32_t tid = tile * kElemThreads + threadIdx.x;
+    const uint32_t nthreads = G.n_hist_tiles * kHistThreads;
+    const uint32_t tid = tile * kHistThreads + threadIdx.x;
     for (uint32_t c = tid; c < G.C; c += nthreads) {
         G.cstart[c] = 0;
         G.cend[c] = 0;
@@ -97,14 +97,13 @@ __global__ __launch_bounds__(kElemThreads) void k_predict(Batch b)
     for (uint32_t s = tid; s < G.nb; s += nthreads) G.born_mark[s] = kNoCell;
     if (tid == 0) *G.cycle_run = cycle;
 
-    for (uint32_t d = threadIdx.x; d < (kElemThreads / kWave) * nbins; d += kElemThreads)
-        cnt[d / nbins][d % nbins] = 0;
+    for (uint32_t d = threadIdx.x; d < nbins; d += kHistThreads) cnt[d] = 0;
     __syncthreads();
 
     float x[kPredItems], y[kPredItems], vx[kPredItems], vy[kPredItems], w[kPredItems];
 #pragma unroll
     for (int it = 0; it < kPredItems; ++it) {
-        const uint32_t i = tile * kHistTile + it * kElemThreads + threadIdx.x;
+        const uint32_t i = tile * kHistTile + it * kHistThreads + threadIdx.x;
         const bool valid = i < G.nu;
         x[it] = valid ? G.x[i] : 0.0f;
         y[it] = valid ? G.y[i] : 0.0f;
@@ -114,7 +113,7 @@ __global__ __launch_bounds__(kElemThreads) void k_predict(Batch b)
     }
 #pragma unroll
     for (int it = 0; it < kPredItems; ++it) {
-        const uint32_t i = tile * kHistTile + it * kElemThreads + threadIdx.x;
+        const uint32_t i = tile * kHistTile + it * kHistThreads + threadIdx.x;
         const bool valid = i < G.nu;
         uint32_t k = 0;
         if (valid) {
@@ -134,14 +133,11 @@ __global__ __launch_bounds__(kElemThreads) void k_predict(Batch b)
             G.w[i] = (k == G.C) ? 0.0f : G.p_s * w[it];
             G.key[i] = k;
         }
-        wave_digit_count(valid, (k >> shift) & (nbins - 1u), bits, cnt[wave]);
+        wave_digit_count(valid, (k >> shift) & (nbins - 1u), bits, cnt);
     }
     __syncthreads();
-    for (uint32_t d = threadIdx.x; d < nbins; d += kElemThreads) {
-        uint32_t t = 0;
-        for (int wv = 0; wv < kElemThreads / kWave; ++wv) t += cnt[wv][d];
-        G.hist[d * G.n_hist_tiles + tile] = t;
-    }
+    for (uint32_t d = threadIdx.x; d < nbins; d += kHistThreads)
+        G.hist[d * G.n_hist_tiles + tile] = cnt[d];
 }
 
 hipError_t launch_predict(const GridRef* g, int n, hipStream_t s)
@@ -149,14 +145,17 @@ hipError_t launch_predict(const GridRef* g, int n, hipStream_t s)
     Batch b;
     const uint32_t blocks =
         make_batch(b, g, n, [](const GridDev& G) { return xcd_blocks(G.n_hist_tiles); });
-    if (blocks) DOGM_LAUNCH(k_predict, dim3(blocks), dim3(kElemThreads), 0, s, b);
+    if (blocks) DOGM_LAUNCH(k_predict, dim3(blocks), dim3(kHistThreads), 0, s, b);
     return hipGetLastError();
 }
 
 // ----------------------------------------------------------------------------------------------
 // Alg. 5: slot allocation from the exact prefix E_c of the fixed-point new-born masses; each cell
-// that receives slots marks its first slot with its id.
+// that receives slots marks its first slot with its id and names itself as the first cell of
+// every new-born tile that starts inside its slot range.
 // ----------------------------------------------------------------------------------------------
+
+__device__ __forceinline__ uint32_t ceil_div_dev(uint32_t a, uint32_t b) { return (a + b - 1) / b; }
 
 // o_c = floor(nu_b E_c / S) in FP64 with every operation rounded separately (no contraction).
 __device__ __forceinline__ uint32_t slot_offset(uint64_t E, uint64_t S, uint32_t nb)
@@ -191,8 +190,13 @@ __global__ __launch_bounds__(kCellThreads) void k_born_offsets(Batch b)
     G.born_off[c] = o;
     if (c < G.C && Stot != 0 && G.nb > 0 && q != 0) {
         const uint32_t o1 = (c + 1 == G.C) ? G.nb : slot_offset(E + q, Stot, G.nb);
-        if (o1 > o) G.born_mark[o] = c;
-        else atomicOr(G.status, kStNoCarrier);
+        if (o1 > o) {
+            G.born_mark[o] = c;
+            for (uint32_t t = ceil_div_dev(o, kBornTile); t * (uint32_t)kBornTile < o1; ++t)
+                G.tile_first[t] = c;
+        } else {
+            atomicOr(G.status, kStNoCarrier);
+        }
     }
 }
 
@@ -206,9 +210,10 @@ hipError_t launch_born_offsets(const GridRef* g, int n, hipStream_t s)
 }
 
 // ----------------------------------------------------------------------------------------------
-// One launch, two kinds of tiles of kResTile elements: persistent tiles normalise the sorted
-// weights (Alg. 4, last loop: w <- p_A mu_A g w + (1 - p_A) mu_UA w), new-born tiles initialise
-// their slots (Alg. 5); both store the fixed-point sum of their weights for the resampling.
+// One launch, two kinds of tiles: persistent tiles of kResTile particles normalise the sorted
+// weights (Alg. 4, last loop: w <- p_A mu_A g w + (1 - p_A) mu_UA w), new-born tiles of
+// kBornTile slots initialise their slots (Alg. 5); both store the fixed-point sum of their
+// weights for the resampling.
 // ----------------------------------------------------------------------------------------------
 
 __device__ __forceinline__ double likelihood(double vx, double vy, double mx, double my,
@@ -257,7 +262,6 @@ __global__ __launch_bounds__(kResThreads) void k_particle_tiles(Batch b)
 {
     __shared__ uint64_t tmp[kResThreads / kWave + 1];
     __shared__ uint32_t wave_last[kResThreads / kWave];
-    __shared__ uint32_t first_cell;
     const int gi = batch_grid(b);
     const GridDev& G = *b.g[gi];
     const MeasDev& M = b.m[gi];
@@ -295,54 +299,31 @@ __global__ __launch_bounds__(kResThreads) void k_particle_tiles(Batch b)
             q += fixed40(wf);
         }
     } else {
-        // new-born slots: the cell of a slot is the last mark at or before it; the block's
-        // first cell comes from a search of the slot offsets, the rest from a running maximum
-        // of the marks (cells are numbered in slot order)
+        // new-born slots, one per thread: the cell of a slot is the last mark at or before it,
+        // or the tile's first cell if there is none (cells are numbered in slot order)
         const uint32_t bt = tile - G.n_res_ptiles;
-        const uint32_t s0 = bt * kResTile;
+        const uint32_t s = bt * kBornTile + threadIdx.x;
         const uint64_t Stot = *G.S_fixed;
         const uint32_t cycle = *G.cycle_run;
-        if (threadIdx.x == 0) {
-            uint32_t lo = 0, hi = G.C;  // born_off[lo] <= s0 < born_off[hi]
-            if (Stot != 0) {
-                while (hi - lo > 1) {
-                    const uint32_t mid = (lo + hi) >> 1;
-                    if (G.born_off[mid] <= s0) lo = mid; else hi = mid;
-                }
-            }
-            first_cell = lo;
-        }
-        __syncthreads();
-        uint32_t carry = first_cell;
-#pragma unroll 1
-        for (int it = 0; it < kResItems; ++it) {
-            const uint32_t s = s0 + it * kResThreads + threadIdx.x;
-            const uint32_t mk = (s < G.nb) ? G.born_mark[s] : kNoCell;
-            // running maximum of the marks within the wave, then across waves and rounds
-            uint32_t m = (mk == kNoCell) ? 0u : mk + 1u;
+        const uint32_t first = G.tile_first[bt];
+        const uint32_t mk = (s < G.nb) ? G.born_mark[s] : kNoCell;
+        uint32_t m = (mk == kNoCell) ? 0u : mk + 1u;
 #pragma unroll
-            for (int off = 1; off < kWave; off <<= 1) {
-                const uint32_t o = __shfl_up(m, off, kWave);
-                if (lane >= off) m = o > m ? o : m;
-            }
-            if (lane == kWave - 1) wave_last[wave] = m;
-            __syncthreads();
-            uint32_t before = 0;
-            for (int w2 = 0; w2 < wave; ++w2) before = wave_last[w2] > before ? wave_last[w2] : before;
-            uint32_t round_max = 0;
-            for (int w2 = 0; w2 < kResThreads / kWave; ++w2)
-                round_max = wave_last[w2] > round_max ? wave_last[w2] : round_max;
-            __syncthreads();
-            m = before > m ? before : m;
-            const uint32_t c = m ? (m - 1u > carry || carry == kNoCell ? m - 1u : carry) : carry;
-            if (round_max) carry = (round_max - 1u > carry) ? round_max - 1u : carry;
-            if (s >= G.nb) continue;
+        for (int off = 1; off < kWave; off <<= 1) {
+            const uint32_t o = __shfl_up(m, off, kWave);
+            if (lane >= off) m = o > m ? o : m;
+        }
+        if (lane == kWave - 1) wave_last[wave] = m;
+        __syncthreads();
+        for (int w2 = 0; w2 < wave; ++w2) m = wave_last[w2] > m ? wave_last[w2] : m;
+        if (s < G.nb) {
             if (Stot == 0) {  // no new-born mass anywhere: empty slots
                 G.bx[s] = G.by[s] = G.bvx[s] = G.bvy[s] = G.bw[s] = 0.0f;
                 G.bkey[s] = G.C;
                 G.bassoc[s] = 0;
             } else {
-                q += fixed40(init_born(G, M, s, c, cycle));
+                const uint32_t c = (m != 0u && m - 1u > first) ? m - 1u : first;
+                q = fixed40(init_born(G, M, s, c, cycle));
             }
         }
     }
@@ -354,7 +335,7 @@ hipError_t launch_particle_tiles(const GridRef* g, int n, hipStream_t s)
 {
     Batch b;
     const uint32_t blocks =
-        make_batch(b, g, n, [](const GridDev& G) { return G.n_res_ptiles + G.n_res_btiles; });
+        make_batch(b, g, n, [](const GridDev& G) { return G.n_res_ptiles + G.n_born_parts; });
     if (blocks) DOGM_LAUNCH(k_particle_tiles, dim3(blocks), dim3(kResThreads), 0, s, b);
     return hipGetLastError();
 }

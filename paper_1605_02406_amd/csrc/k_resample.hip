@@ -5,11 +5,12 @@
 // the weights.  Draw j sits at u_j = (j + U) d with the spacing d = W / nu rounded once to FP64,
 // and selects the first particle i with F_i > floor(u_j); for nu < 2^28 the last draw stays
 // below W by more than the rounding of d and of the product, so every draw finds a particle.
-// Instead of a search per draw, every source particle computes the range of draws that land in
-// its CDF interval, J(F_{i-1}) <= j < J(F_i) with J(F) = min{ j : floor(u_j) >= F }, and writes
-// its copies there.
-// One kernel: each tile adds up the totals of the tiles before it, scans its own weights with
-// wave prefix sums and scatters; reads are coalesced and the writes of a wave advance together.
+// Source i receives the draws J(F_{i-1}) <= j < J(F_i) with J(F) = min{ j : floor(u_j) >= F }.
+// One kernel: each tile adds up the totals of the tiles before it and scans its own weights
+// with wave prefix sums.  The draws of a wave's sources form one contiguous range; the wave
+// walks it in windows: every lane writes the local index of each of its sources into the
+// window's LDS map at the source's draws, then the wave writes the window's outputs in order,
+// so stores are coalesced and source reads ascend.
 #include "launch.h"
 
 namespace dogm {
@@ -34,10 +35,15 @@ __device__ __forceinline__ uint32_t first_draw_at(uint64_t F, double U, double s
     return j;
 }
 
+constexpr int kResWindow = 1024;  // draws per LDS map window of a wave
+
 __global__ __launch_bounds__(kResThreads) void k_resample(Batch b)
 {
+    constexpr int kSrc = kResRounds * kWave;  // sources per wave
+    static_assert(kSrc <= 65536, "local source indices are 16-bit");
     __shared__ uint64_t tmp[kResWaves + 1];
     __shared__ uint64_t wave_tot[kResWaves];
+    __shared__ uint16_t srcmap[kResWaves][kResWindow];
     const int gi = batch_grid(b);
     const GridDev& G = *b.g[gi];
     const uint32_t ntiles = G.n_res_ptiles + G.n_res_btiles;
@@ -51,21 +57,32 @@ __global__ __launch_bounds__(kResThreads) void k_resample(Batch b)
     const int lane = lane_id();
     const int wave = threadIdx.x / kWave;
 
-    // joint weight before this tile and in total
+    // joint weight before this tile and in total, from the partial sums of the persistent tiles
+    // (kResTile particles each) and of the new-born tiles (kBornTile slots each)
+    const bool born = tile >= G.n_res_ptiles;
+    const uint32_t t_local = born ? tile - G.n_res_ptiles : tile;
+    const uint32_t nparts = G.n_res_ptiles + G.n_born_parts;
+    const uint32_t limit = born ? G.n_res_ptiles + t_local * (kResTile / kBornTile) : tile;
     uint64_t before = 0, all = 0;
-    for (uint32_t t = threadIdx.x; t < ntiles; t += kResThreads) {
-        const uint64_t v = G.rpart[t];
-        all += v;
-        if (t < tile) before += v;
+    for (uint32_t t0 = threadIdx.x; t0 < nparts; t0 += 4 * kResThreads) {
+        uint64_t v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const uint32_t t = t0 + u * kResThreads;
+            v[u] = t < nparts ? G.rpart[t] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            all += v[u];
+            if (t0 + u * kResThreads < limit) before += v[u];
+        }
     }
     before = block_sum(before, tmp);
     const uint64_t W = block_sum(all, tmp);
     if (tile == 0 && threadIdx.x == 0) *G.W_fixed = W;
 
-    const bool born = tile >= G.n_res_ptiles;
-    const uint32_t t_local = born ? tile - G.n_res_ptiles : tile;
     const uint32_t n_src = born ? G.nb : nu;
-    const uint32_t wbase = t_local * kResTile + wave * (kResRounds * kWave);
+    const uint32_t wbase = t_local * kResTile + wave * kSrc;
 
     if (W == 0) {  // nothing carries weight: keep the sorted persistent set as it is
         if (!born) {
@@ -80,58 +97,74 @@ __global__ __launch_bounds__(kResThreads) void k_resample(Batch b)
                 }
             }
         }
-    } else {
-        const float* wsrc = born ? G.bw : G.sw;
-        uint64_t q[kResRounds];
-        uint64_t wsum = 0;
-#pragma unroll
-        for (int r = 0; r < kResRounds; ++r) {
-            const uint32_t i = wbase + r * kWave + lane;
-            q[r] = i < n_src ? fixed40(wsrc[i]) : 0;
-            wsum += q[r];
-        }
-        wsum = wave_sum(wsum);
-        if (lane == 0) wave_tot[wave] = wsum;
-        __syncthreads();
-        uint64_t run = before;
-        for (int w2 = 0; w2 < wave; ++w2) run += wave_tot[w2];
+        return;
+    }
 
-        const double U = (double)unit_f32(draw(G, 0u, cycle, kPurposeResample).x);
-        const double spacing = __ddiv_rn((double)W, (double)nu);
-        const double inv_spacing = 1.0 / spacing;
-        const float out_w = (float)((double)W * 0x1p-40 / (double)nu);
-        const float* px = born ? G.bx : G.sx;
-        const float* py = born ? G.by : G.sy;
-        const float* pvx = born ? G.bvx : G.svx;
-        const float* pvy = born ? G.bvy : G.svy;
-        float ax[kResRounds], ay[kResRounds], avx[kResRounds], avy[kResRounds];
+    const float* wsrc = born ? G.bw : G.sw;
+    uint64_t q[kResRounds];
+    uint64_t wsum = 0;
+#pragma unroll
+    for (int r = 0; r < kResRounds; ++r) {
+        const uint32_t i = wbase + r * kWave + lane;
+        q[r] = i < n_src ? fixed40(wsrc[i]) : 0;
+        wsum += q[r];
+    }
+    wsum = wave_sum(wsum);
+    if (lane == 0) wave_tot[wave] = wsum;
+    __syncthreads();
+    uint64_t run = before;
+    for (int w2 = 0; w2 < wave; ++w2) run += wave_tot[w2];
+
+    const double U = (double)unit_f32(draw(G, 0u, cycle, kPurposeResample).x);
+    const double spacing = __ddiv_rn((double)W, (double)nu);
+    const double inv_spacing = 1.0 / spacing;
+    const float out_w = (float)((double)W * 0x1p-40 / (double)nu);
+
+    // draws [j0, j1) of every source of this wave (local source r * 64 + lane); they tile the
+    // wave's range [j_begin, j_end) in source order
+    uint32_t j0[kResRounds], j1[kResRounds];
+#pragma unroll
+    for (int r = 0; r < kResRounds; ++r) {
+        const uint64_t incl = wave_incl_scan(q[r]);
+        const uint64_t F_lo = run + incl - q[r];
+        run += __shfl(incl, kWave - 1, kWave);
+        j0[r] = first_draw_at(F_lo, U, spacing, inv_spacing, nu);
+    }
+    const uint32_t j_end = first_draw_at(run, U, spacing, inv_spacing, nu);
+#pragma unroll
+    for (int r = 0; r < kResRounds; ++r) {
+        const uint32_t next_lane = __shfl_down(j0[r], 1, kWave);
+        const uint32_t next_round = (r + 1 < kResRounds) ? __shfl(j0[r + 1 < kResRounds ? r + 1 : r], 0, kWave) : j_end;
+        j1[r] = lane < kWave - 1 ? next_lane : next_round;
+    }
+    const uint32_t j_begin = __shfl(j0[0], 0, kWave);
+
+    const float* px = born ? G.bx : G.sx;
+    const float* py = born ? G.by : G.sy;
+    const float* pvx = born ? G.bvx : G.svx;
+    const float* pvy = born ? G.bvy : G.svy;
+    uint16_t* map = srcmap[wave];
+    for (uint32_t wb = j_begin; wb < j_end; wb += kResWindow) {
+        const uint32_t we = min(wb + (uint32_t)kResWindow, j_end);
 #pragma unroll
         for (int r = 0; r < kResRounds; ++r) {
-            const uint32_t i = wbase + r * kWave + lane;
-            const bool ok = i < n_src && q[r] != 0;
-            ax[r] = ok ? px[i] : 0.0f;
-            ay[r] = ok ? py[i] : 0.0f;
-            avx[r] = ok ? pvx[i] : 0.0f;
-            avy[r] = ok ? pvy[i] : 0.0f;
+            const uint32_t lo = j0[r] > wb ? j0[r] : wb;
+            const uint32_t hi = j1[r] < we ? j1[r] : we;
+            for (uint32_t j = lo; j < hi; ++j) map[j - wb] = (uint16_t)(r * kWave + lane);
         }
-#pragma unroll
-        for (int r = 0; r < kResRounds; ++r) {
-            const uint32_t i = wbase + r * kWave + lane;
-            const uint64_t incl = wave_incl_scan(q[r]);
-            const uint64_t F_hi = run + incl;
-            const uint64_t F_lo = F_hi - q[r];
-            run += __shfl(incl, kWave - 1, kWave);
-            if (i >= n_src || q[r] == 0) continue;
-            const uint32_t j0 = first_draw_at(F_lo, U, spacing, inv_spacing, nu);
-            const uint32_t j1 = first_draw_at(F_hi, U, spacing, inv_spacing, nu);
-            for (uint32_t j = j0; j < j1; ++j) {
-                G.x[j] = ax[r];
-                G.y[j] = ay[r];
-                G.vx[j] = avx[r];
-                G.vy[j] = avy[r];
-                G.w[j] = out_w;
-            }
+        // the map is written and read by this wave only
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        for (uint32_t j = wb + lane; j < we; j += kWave) {
+            const uint32_t i = wbase + map[j - wb];
+            G.x[j] = px[i];
+            G.y[j] = py[i];
+            G.vx[j] = pvx[i];
+            G.vy[j] = pvy[i];
+            G.w[j] = out_w;
         }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+        __builtin_amdgcn_wave_barrier();
     }
 }
 

@@ -1,10 +1,12 @@
 // Alg. 2, first line: stable sort of the particles by cell key.
 //
 // LSD radix sort over digits of at most kSortBits bits (two passes for grids up to 2^20 cells);
-// each pass moves keys, source indices and the whole FP32 particle state.  A pass is three
-// kernels that communicate only through memory: the digit histogram of every tile (for the
-// first pass it comes from the prediction kernel), a scan of each digit's row of tile counts,
-// and the scatter.  No block waits for another.
+// each pass moves only the key and the source index.  A pass is three kernels that communicate
+// only through memory: the digit histogram of every tile (for the first pass it comes from the
+// prediction kernel), a scan of each digit's row of tile counts, and the scatter.  No block
+// waits for another.  A last kernel gathers the FP32 particle state into sorted order through
+// the permutation; the particles arrive from the resampling nearly in cell order, so the
+// permutation mostly ascends and the gather reads whole cache lines.
 //
 // Stable ranking inside a tile: each wave owns a contiguous quarter of the tile (1024 keys) and
 // walks it 64 keys at a time; lanes holding the same digit find each other with one ballot per
@@ -21,104 +23,93 @@ constexpr int kSortWaves = kSortThreads / kWave;
 struct SortArrays {
     const uint32_t* ik;
     const uint32_t* iv;  // null: the source index is the element index
-    const float *ix, *iy, *ivx, *ivy, *iw;
     uint32_t *ok, *ov;
-    float *ox, *oy, *ovx, *ovy, *ow;
 };
 
-// Pass p of P reads the predicted state (p == 0) or the previous pass's output and writes the
-// sorted arrays on the last pass; the passes alternate between the sorted and the temporary
-// arrays so that the last one lands in the sorted arrays.
+// Pass p of P reads the predicted keys (p == 0) or the previous pass's output and writes the
+// sorted keys and permutation on the last pass; the passes alternate between the sorted and
+// the temporary arrays so that the last one lands in the sorted arrays.
 __device__ __forceinline__ SortArrays sort_arrays(const GridDev& G, uint32_t pass)
 {
     const bool dst_sorted = ((G.passes - 1 - pass) & 1u) == 0;
     SortArrays a;
     if (pass == 0) {
         a.ik = G.key; a.iv = nullptr;
-        a.ix = G.x; a.iy = G.y; a.ivx = G.vx; a.ivy = G.vy; a.iw = G.w;
     } else if (dst_sorted) {
         a.ik = G.tkey; a.iv = G.tval;
-        a.ix = G.tx; a.iy = G.ty; a.ivx = G.tvx; a.ivy = G.tvy; a.iw = G.tw;
     } else {
         a.ik = G.skey; a.iv = G.perm;
-        a.ix = G.sx; a.iy = G.sy; a.ivx = G.svx; a.ivy = G.svy; a.iw = G.sw;
     }
     if (dst_sorted) {
         a.ok = G.skey; a.ov = G.perm;
-        a.ox = G.sx; a.oy = G.sy; a.ovx = G.svx; a.ovy = G.svy; a.ow = G.sw;
     } else {
         a.ok = G.tkey; a.ov = G.tval;
-        a.ox = G.tx; a.oy = G.ty; a.ovx = G.tvx; a.ovy = G.tvy; a.ow = G.tw;
     }
     return a;
 }
 
-// Digit histogram of every 1024-key sub-tile of the keys a pass (>= 1) reads.
-constexpr int kHistItems = kHistTile / kSortThreads;  // 4
+// Digit histogram of every tile of the keys a pass (>= 1) reads.
+constexpr int kHistItems = kHistTile / kHistThreads;  // 4
 
-__global__ __launch_bounds__(kSortThreads) void k_sort_hist(Batch b, uint32_t pass)
+__global__ __launch_bounds__(kHistThreads) void k_sort_hist(Batch b, uint32_t pass)
 {
-    __shared__ uint32_t cnt[kSortWaves][kSortBins];
+    __shared__ uint32_t cnt[kSortBins];
     const int gi = batch_grid(b);
     const GridDev& G = *b.g[gi];
-    const uint32_t tile = blockIdx.x - b.bstart[gi];
+    // neighbouring tiles write neighbouring words of every digit row: keep them on one XCD so
+    // the partial lines meet in its L2
+    const uint32_t tile = xcd_tile(b, gi);
+    if (tile >= G.n_hist_tiles) return;
     const uint32_t shift = G.dshift[pass], bits = G.dbits[pass], nbins = 1u << bits;
-    const int wave = threadIdx.x / kWave;
-    for (uint32_t d = threadIdx.x; d < kSortWaves * nbins; d += kSortThreads)
-        cnt[d / nbins][d % nbins] = 0;
+    for (uint32_t d = threadIdx.x; d < nbins; d += kHistThreads) cnt[d] = 0;
     __syncthreads();
     const uint32_t* keys = sort_arrays(G, pass).ik;
     uint32_t k[kHistItems];
 #pragma unroll
     for (int it = 0; it < kHistItems; ++it) {
-        const uint32_t i = tile * kHistTile + it * kSortThreads + threadIdx.x;
+        const uint32_t i = tile * kHistTile + it * kHistThreads + threadIdx.x;
         k[it] = i < G.nu ? keys[i] : 0u;
     }
 #pragma unroll
     for (int it = 0; it < kHistItems; ++it) {
-        const uint32_t i = tile * kHistTile + it * kSortThreads + threadIdx.x;
-        wave_digit_count(i < G.nu, (k[it] >> shift) & (nbins - 1u), bits, cnt[wave]);
+        const uint32_t i = tile * kHistTile + it * kHistThreads + threadIdx.x;
+        wave_digit_count(i < G.nu, (k[it] >> shift) & (nbins - 1u), bits, cnt);
     }
     __syncthreads();
-    for (uint32_t d = threadIdx.x; d < nbins; d += kSortThreads) {
-        uint32_t t = 0;
-        for (int w = 0; w < kSortWaves; ++w) t += cnt[w][d];
-        G.hist[d * G.n_hist_tiles + tile] = t;
-    }
+    for (uint32_t d = threadIdx.x; d < nbins; d += kHistThreads)
+        G.hist[d * G.n_hist_tiles + tile] = cnt[d];
 }
 
-// Each wave turns one digit's row of tile counts into exclusive prefixes and stores the row's
-// total.
-constexpr int kRowsPerBlock = kScanRowThreads / kWave;
+// Each block turns one digit's row of tile counts into exclusive prefixes (each thread scans
+// kRowItems consecutive entries, then one block-wide scan) and stores the row's total.
 constexpr int kRowItems = 8;
 
 __global__ __launch_bounds__(kScanRowThreads) void k_scan_rows(Batch b, uint32_t pass)
 {
+    __shared__ uint32_t tmp[kScanRowThreads / kWave + 1];
     const int gi = batch_grid(b);
     const GridDev& G = *b.g[gi];
-    const uint32_t d = (blockIdx.x - b.bstart[gi]) * kRowsPerBlock + threadIdx.x / kWave;
-    if (d >= (1u << G.dbits[pass])) return;
-    const int lane = lane_id();
+    const uint32_t d = blockIdx.x - b.bstart[gi];
     uint32_t* row = G.hist + (size_t)d * G.n_hist_tiles;
     uint32_t carry = 0;
-    for (uint32_t base = 0; base < G.n_hist_tiles; base += kWave * kRowItems) {
-        const uint32_t t0 = base + lane * kRowItems;
+    for (uint32_t base = 0; base < G.n_hist_tiles; base += kScanRowThreads * kRowItems) {
+        const uint32_t t0 = base + threadIdx.x * kRowItems;
         uint32_t v[kRowItems], acc = 0;
 #pragma unroll
         for (int j = 0; j < kRowItems; ++j) {
             v[j] = (t0 + j < G.n_hist_tiles) ? row[t0 + j] : 0u;
             acc += v[j];
         }
-        const uint32_t incl = wave_incl_scan(acc);
-        uint32_t run = carry + incl - acc;
+        uint32_t total;
+        uint32_t run = carry + block_excl_scan(acc, tmp, &total);
 #pragma unroll
         for (int j = 0; j < kRowItems; ++j) {
             if (t0 + j < G.n_hist_tiles) row[t0 + j] = run;
             run += v[j];
         }
-        carry += __shfl(incl, kWave - 1, kWave);
+        carry += total;
     }
-    if (lane == 0) G.rowtot[d] = carry;
+    if (threadIdx.x == 0) G.rowtot[d] = carry;
 }
 
 // Writes one payload array in destination order: every element goes to its local sorted slot in
@@ -166,18 +157,12 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(Batch b, uint32_t
     const SortArrays A = sort_arrays(G, pass);
     const uint32_t base = tile * kSortTile + wave * (kSortTile / kSortWaves);
     uint32_t k[kSortItems], v[kSortItems], rank[kSortItems];
-    float px[kSortItems], py[kSortItems], pvx[kSortItems], pvy[kSortItems], pw[kSortItems];
 #pragma unroll
     for (int it = 0; it < kSortItems; ++it) {
         const uint32_t idx = base + it * kWave + lane;
         const bool valid = idx < G.nu;
         k[it] = valid ? A.ik[idx] : 0u;
         v[it] = valid ? (A.iv ? A.iv[idx] : idx) : 0u;
-        px[it] = valid ? A.ix[idx] : 0.0f;
-        py[it] = valid ? A.iy[idx] : 0.0f;
-        pvx[it] = valid ? A.ivx[idx] : 0.0f;
-        pvy[it] = valid ? A.ivy[idx] : 0.0f;
-        pw[it] = valid ? A.iw[idx] : 0.0f;
     }
     // stable ranks inside the wave's quarter
 #pragma unroll
@@ -272,13 +257,53 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(Batch b, uint32_t
             }
         }
     }
-    // the payload, one array at a time through the same LDS row
+    // the source indices through the same LDS row
     move_out(v, A.ov, stage, lpos, gpos);
-    move_out(px, A.ox, stage, lpos, gpos);
-    move_out(py, A.oy, stage, lpos, gpos);
-    move_out(pvx, A.ovx, stage, lpos, gpos);
-    move_out(pvy, A.ovy, stage, lpos, gpos);
-    move_out(pw, A.ow, stage, lpos, gpos);
+}
+
+// The particle state in sorted order, s*[i] = *[perm[i]], and the particle range of every cell
+// (its first and one-past-last sorted position; the prediction cleared them, so empty cells keep
+// start == end).
+constexpr int kGatherItems = 4;
+
+__global__ __launch_bounds__(kElemThreads) void k_sort_gather(Batch b)
+{
+    const int gi = batch_grid(b);
+    const GridDev& G = *b.g[gi];
+    const uint32_t tile = xcd_tile(b, gi);
+    uint32_t src[kGatherItems];
+#pragma unroll
+    for (int it = 0; it < kGatherItems; ++it) {
+        const uint32_t i = (tile * kGatherItems + it) * kElemThreads + threadIdx.x;
+        src[it] = i < G.nu ? G.perm[i] : 0u;
+    }
+    float x[kGatherItems], y[kGatherItems], vx[kGatherItems], vy[kGatherItems], w[kGatherItems];
+#pragma unroll
+    for (int it = 0; it < kGatherItems; ++it) {
+        const uint32_t i = (tile * kGatherItems + it) * kElemThreads + threadIdx.x;
+        const bool ok = i < G.nu;
+        x[it] = ok ? G.x[src[it]] : 0.0f;
+        y[it] = ok ? G.y[src[it]] : 0.0f;
+        vx[it] = ok ? G.vx[src[it]] : 0.0f;
+        vy[it] = ok ? G.vy[src[it]] : 0.0f;
+        w[it] = ok ? G.w[src[it]] : 0.0f;
+    }
+#pragma unroll
+    for (int it = 0; it < kGatherItems; ++it) {
+        const uint32_t i = (tile * kGatherItems + it) * kElemThreads + threadIdx.x;
+        if (i < G.nu) {
+            G.sx[i] = x[it];
+            G.sy[i] = y[it];
+            G.svx[i] = vx[it];
+            G.svy[i] = vy[it];
+            G.sw[i] = w[it];
+            const uint32_t k = G.skey[i];
+            if (k < G.C) {
+                if (i == 0 || G.skey[i - 1] != k) G.cstart[k] = i;
+                if (i + 1 == G.nu || G.skey[i + 1] != k) G.cend[k] = i + 1;
+            }
+        }
+    }
 }
 
 hipError_t launch_sort(const GridRef* g, int n, hipStream_t s)
@@ -306,12 +331,12 @@ hipError_t launch_sort(const GridRef* g, int n, hipStream_t s)
             }
         Batch b;
         if (pass > 0) {
-            const uint32_t hb = make_batch(b, sub, m, [](const GridDev& G) { return G.n_hist_tiles; });
-            if (hb) DOGM_LAUNCH(k_sort_hist, dim3(hb), dim3(kSortThreads), 0, s, b, pass);
+            const uint32_t hb =
+                make_batch(b, sub, m, [](const GridDev& G) { return xcd_blocks(G.n_hist_tiles); });
+            if (hb) DOGM_LAUNCH(k_sort_hist, dim3(hb), dim3(kHistThreads), 0, s, b, pass);
         }
-        const uint32_t rows = make_batch(b, sub, m, [pass](const GridDev& G) {
-            return ceil_div(1u << G.dbits[pass], kRowsPerBlock);
-        });
+        const uint32_t rows =
+            make_batch(b, sub, m, [pass](const GridDev& G) { return 1u << G.dbits[pass]; });
         if (rows) DOGM_LAUNCH(k_scan_rows, dim3(rows), dim3(kScanRowThreads), 0, s, b, pass);
         const uint32_t tiles =
             make_batch(b, sub, m, [](const GridDev& G) { return xcd_blocks(G.n_sort_tiles); });
@@ -320,6 +345,11 @@ hipError_t launch_sort(const GridRef* g, int n, hipStream_t s)
             sizeof(uint32_t) * ((size_t)kSortWaves * nbins + 2 * nbins + kSortTile);
         if (tiles) DOGM_LAUNCH(k_sort_scatter, dim3(tiles), dim3(kSortThreads), lds, s, b, pass);
     }
+    Batch b;
+    const uint32_t blocks = make_batch(b, g, n, [](const GridDev& G) {
+        return xcd_blocks(ceil_div(G.nu, kGatherItems * kElemThreads));
+    });
+    if (blocks) DOGM_LAUNCH(k_sort_gather, dim3(blocks), dim3(kElemThreads), 0, s, b);
     return hipGetLastError();
 }
 

@@ -114,6 +114,11 @@ class PerCall:
         perm, start, end = oracle.assign(key, p.C)
         assert np.array_equal(u32(g.v["perm"]), perm.astype(np.uint32)), "permutation"
         assert np.array_equal(u32(g.v["skey"]), key[perm]), "sorted keys"
+        gs, ge = u32(g.v["cell_start"]), u32(g.v["cell_end"])
+        ne = end > start  # empty cells: only start == end is promised
+        assert np.array_equal(gs[ne], start[ne]), "cell starts"
+        assert np.array_equal(ge[ne], end[ne]), "cell ends"
+        assert np.array_equal(gs[~ne], ge[~ne]), "empty cells"
         srt = g.state(sorted_=True)
         for c in ("x", "y", "vx", "vy", "w"):
             assert np.array_equal(srt[c], st[c][perm]), f"sorted {c}"
@@ -127,12 +132,6 @@ class PerCall:
         mz = meas_numpy(meas)
         g.update(meas)
         torch.cuda.synchronize()
-        # the per-cell pass records the particle range of every cell
-        gs, ge = u32(g.v["cell_start"]), u32(g.v["cell_end"])
-        ne = end > start  # empty cells: only start == end is promised
-        assert np.array_equal(gs[ne], start[ne]), "cell starts"
-        assert np.array_equal(ge[ne], end[ne]), "cell ends"
-        assert np.array_equal(gs[~ne], ge[~ne]), "empty cells"
         cu = oracle.cell_update(p, srt["w"], start, end, m_F_prev, mz["m_occ"], mz["m_free"])
         for c in ("m_pO", "m_pF", "m_O", "m_F", "rho_b", "rho_p", "pign"):
             self.stats[f"update.{c}"] = assert_close(f"update {c}", host(g.v[c]), cu[c],
