@@ -8,11 +8,15 @@ timed region.  Prints one JSON line.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--cpu-cycles N] [--copy-calibration]
 
-The roofline object covers the kernel that takes the most time per cycle (found from a traced
-warm-up): its launches inside the timed region are bracketed by HIP events on their own stream,
-and its algorithmic bytes per launch (the per-particle / per-cell figures below, times the units
-one launch processes) are divided by the mean launch duration.  HBM traffic comes from the
-committed counter summary of that kernel when its source has not changed since.
+The timed region replays K cycles captured as HIP graphs (one graph per cycle, each with its own
+measurement grid), so host launch overhead is out of the loop; the same K cycles stepped call by
+call are timed before it and reported as `eager`.  The roofline object covers the kernel that
+takes the most time per cycle (found from a traced warm-up): its launches in the eager cycles are
+bracketed by HIP events on their own stream (event records captured inside a graph do not
+bracket the kernel nodes on this stack), and its algorithmic bytes per launch (the
+per-particle / per-cell figures below, times the units one launch processes) are divided by the
+mean launch duration.  HBM traffic comes from the committed counter summary of
+that kernel when its source has not changed since.
 """
 from __future__ import annotations
 
@@ -39,7 +43,7 @@ B_PER_CELL = 92
 CSRC = os.path.join(ROOT, "paper_1605_02406_amd", "csrc")
 KERNEL_SOURCE = {
     "k_predict": "k_particles.hip", "k_sort_hist": "k_sort.hip", "k_scan_rows": "k_sort.hip",
-    "k_sort_scatter": "k_sort.hip", "k_sort_gather": "k_sort.hip", "k_seg_sums<false>": "k_cells.hip",
+    "k_sort_scatter": "k_sort.hip", "k_cell_ranges": "k_sort.hip", "k_seg_sums<false>": "k_cells.hip",
     "k_seg_sums<true>": "k_cells.hip", "k_cells<false>": "k_cells.hip",
     "k_cells<true>": "k_cells.hip", "k_seg_moments": "k_cells.hip",
     "k_born_offsets": "k_particles.hip", "k_particle_tiles": "k_particles.hip",
@@ -62,9 +66,9 @@ def sort_plan(C: int, max_bits: int = 11):
 def algorithmic_bytes(kernel: str, nu: int, nb: int, C: int) -> float:
     """Algorithmic bytes of ONE launch of `kernel` on one grid (averaged over the launches of a
     cycle where they differ), from per-unit figures: predict reads x, y, vx, vy, w (20 B) and
-    writes them and the key (24 B); a sort pass reads the key and the source index (from the
-    second pass on) and writes both (8 B); the gather reads the permutation and the five
-    state arrays (24 B) and writes the sorted state (20 B); the
+    writes them and the key (24 B); a sort pass reads the key, the source index (from the
+    second pass on) and the five state arrays and writes key, index and state (28 B); the
+    cell ranges read the sorted keys (4 B) and write two words per cell (8 B); the
     resampling reads every joint weight (4 B), the state of each chosen source (16 B) and
     writes the 20-byte state of every output; the per-cell sums read the sorted key, weight
     and velocity (16 B per particle) and write ranges and six FP64 sums per cell (56 B); the
@@ -74,10 +78,10 @@ def algorithmic_bytes(kernel: str, nu: int, nb: int, C: int) -> float:
     if kernel == "k_predict":
         return 44.0 * nu
     if kernel == "k_sort_scatter":
-        per = [(4 if q == 0 else 8) + 8 for q in range(len(bits))]
+        per = [(24 if q == 0 else 28) + 28 for q in range(len(bits))]
         return nu * sum(per) / len(per)
-    if kernel == "k_sort_gather":
-        return 44.0 * nu
+    if kernel == "k_cell_ranges":
+        return 4.0 * nu + 8.0 * C
     if kernel == "k_sort_hist":
         return 4.0 * nu
     if kernel == "k_scan_rows":
@@ -150,7 +154,7 @@ def main():
                          seed=wl.get("seed", 0), **scenes.FILTER)
     C = wl["nx"] * wl["ny"]
     nu, nb = wl["n_pers"], wl["n_born"]
-    n_cycles = args.warmup + args.steps
+    n_cycles = args.warmup + 2 * args.steps
     print(f"[bench] generating {n_cycles} measurement grids", file=sys.stderr, flush=True)
     t_gen = time.perf_counter()
     seq = scenes.measurement_sequence(wl, n_cycles)
@@ -177,10 +181,9 @@ def main():
     launches = {k: len(v) // max(n_traced, 1) for k, v in per_kernel.items()}
     dominant = max(per_kernel_ms, key=per_kernel_ms.get) if per_kernel_ms else "k_predict"
 
-    # timed region: every call of every step, HIP events between the calls on the grid's
-    # stream (the current stream) and around every launch of the dominant kernel
-    print(f"[bench] timing {args.steps} cycles (dominant kernel {dominant})", file=sys.stderr,
-          flush=True)
+    # eager reference: the calls of every step launched from the host, HIP events between the
+    # calls on the grid's stream (the current stream)
+    print(f"[bench] eager {args.steps} cycles", file=sys.stderr, flush=True)
     names = ["predict", "assign", "update", "moments", "resample"]
     ev = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(args.steps)]
     dom = dogm.KernelTrace(dominant, capacity=args.steps * max(launches.get(dominant, 1), 1))
@@ -202,13 +205,34 @@ def main():
             g.resample()
             e[5].record()
         torch.cuda.synchronize()
+    eager_wall = time.perf_counter() - t0
+
+    # timed region: the next K cycles captured one graph per cycle, replayed back to back
+    print(f"[bench] capturing {args.steps} cycles", file=sys.stderr, flush=True)
+    side = torch.cuda.Stream()
+    graphs = []
+    for s in range(args.steps):
+        gr = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(gr, stream=side):
+            g.step(meas[args.warmup + args.steps + s])
+        graphs.append(gr)
+    gev = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(args.steps)]
+    print(f"[bench] timing {args.steps} graph replays", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        gev[s][0].record()
+        graphs[s].replay()
+        gev[s][1].record()
+    torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     status = g.status()
     print("[bench] timed region done", file=sys.stderr, flush=True)
 
     per_call = {n: float(np.mean([ev[s][i].elapsed_time(ev[s][i + 1]) for s in range(args.steps)]))
                 for i, n in enumerate(names)}
-    cycle_ms = [ev[s][0].elapsed_time(ev[s][5]) for s in range(args.steps)]
+    eager_cycle_ms = [ev[s][0].elapsed_time(ev[s][5]) for s in range(args.steps)]
+    cycle_ms = [gev[s][0].elapsed_time(gev[s][1]) for s in range(args.steps)]
     ms_per_step = wall * 1e3 / args.steps
     cycles_per_s = args.steps / wall
     b_alg = B_PER_PARTICLE * nu + B_PER_BORN * nb + B_PER_CELL * C
@@ -249,7 +273,11 @@ def main():
         "all_particles_per_s": cycles_per_s * (nu + nb),
         "cycle_ms_p50": float(np.percentile(cycle_ms, 50)),
         "cycle_ms_p99": float(np.percentile(cycle_ms, 99)),
-        "per_call_ms": per_call,
+        "eager": {"ms_per_step": eager_wall * 1e3 / args.steps,
+                  "cycles_per_s": args.steps / eager_wall,
+                  "cycle_ms_p50": float(np.percentile(eager_cycle_ms, 50)),
+                  "cycle_ms_p99": float(np.percentile(eager_cycle_ms, 99)),
+                  "per_call_ms": per_call},
         "per_kernel_ms": per_kernel_ms,
         "launches_per_cycle": launches,
         "cycle_roofline": {"bound": "hbm", "algorithmic_bytes": b_alg,

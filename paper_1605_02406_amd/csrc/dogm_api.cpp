@@ -118,9 +118,10 @@ GridDev describe(const dogm_params* p, char* base, size_t* bytes)
     Layout L;
     L.take(sizeof(GridDev));
     const size_t f_nu = 4ull * nu, f_nb = 4ull * nb, f_c = 4ull * C, d_c = 8ull * C;
-    float** pf_nu[] = {&d.x, &d.y, &d.vx, &d.vy, &d.w, &d.sx, &d.sy, &d.svx, &d.svy, &d.sw};
-    size_t o_pf_nu[10];
-    for (int i = 0; i < 10; ++i) o_pf_nu[i] = L.take(f_nu);
+    float** pf_nu[] = {&d.x, &d.y, &d.vx, &d.vy, &d.w, &d.sx, &d.sy, &d.svx, &d.svy, &d.sw,
+                       &d.tx, &d.ty, &d.tvx, &d.tvy, &d.tw};
+    size_t o_pf_nu[15];
+    for (int i = 0; i < 15; ++i) o_pf_nu[i] = L.take(f_nu);
     uint32_t** pu_nu[] = {&d.key, &d.skey, &d.perm, &d.tkey, &d.tval};
     size_t o_pu_nu[5];
     for (int i = 0; i < 5; ++i) o_pu_nu[i] = L.take(f_nu);
@@ -151,7 +152,7 @@ GridDev describe(const dogm_params* p, char* base, size_t* bytes)
     *bytes = L.total;
     if (!base) return d;
 
-    for (int i = 0; i < 10; ++i) *pf_nu[i] = at<float>(base, o_pf_nu[i]);
+    for (int i = 0; i < 15; ++i) *pf_nu[i] = at<float>(base, o_pf_nu[i]);
     for (int i = 0; i < 5; ++i) *pu_nu[i] = at<uint32_t>(base, o_pu_nu[i]);
     for (int i = 0; i < 2; ++i) *pu_c[i] = at<uint32_t>(base, o_pu_c[i]);
     for (int i = 0; i < 4; ++i) *pd_c[i] = at<double>(base, o_pd_c[i]);

@@ -26,8 +26,8 @@ constexpr uint32_t kPurposeInit = 0, kPurposePredict = 1, kPurposeBirth = 2,
 constexpr uint32_t kStConflict = 1u, kStNoCarrier = 2u, kStNonFinite = 4u, kStInternal = 8u;
 
 // Radix sort of the cell keys: tiles of kSortTile keys, digits of at most kSortBits bits.
-constexpr int kSortThreads = 256;
-constexpr int kSortItems = 16;
+constexpr int kSortThreads = 1024;
+constexpr int kSortItems = 4;
 constexpr int kSortTile = kSortThreads * kSortItems;  // 4096
 constexpr int kSortBits = 11;
 constexpr int kSortBins = 1 << kSortBits;  // 2048
@@ -77,7 +77,8 @@ struct GridDev {
     // particles sorted by cell
     float *sx, *sy, *svx, *svy, *sw;
     uint32_t *skey, *perm;
-    // ping-pong partner of the sorted keys and permutation during the sort
+    // ping-pong partner of the sorted arrays during the sort
+    float *tx, *ty, *tvx, *tvy, *tw;
     uint32_t *tkey, *tval;
     // cells
     uint32_t *cstart, *cend;
@@ -127,6 +128,8 @@ __device__ __forceinline__ int batch_grid(const Batch& b)
     for (int i = 1; i < b.n; ++i) gi = (blockIdx.x >= b.bstart[i]) ? i : gi;
     return gi;
 }
+
+__device__ __forceinline__ uint32_t ceil_div_u32(uint32_t a, uint32_t b) { return (a + b - 1) / b; }
 
 // Workgroups are dealt to the eight XCDs (each with its own L2) in turn.  For kernels whose
 // neighbouring tiles share data (adjacent output runs, overlapping inputs), each grid's blocks
@@ -242,20 +245,11 @@ __device__ __forceinline__ int32_t wave_max(int32_t v)
     return v;
 }
 
-// Adds this wave's count of every digit to the block's LDS histogram cnt[d]: lanes holding the
-// same digit find each other with one ballot per digit bit, and the lowest of them adds their
-// number with one LDS atomic.
-__device__ __forceinline__ void wave_digit_count(bool valid, uint32_t d, uint32_t bits,
-                                                 uint32_t* cnt)
+// Adds one key's digit to the block's LDS histogram (counts need no order, so a plain LDS
+// atomic; lanes that hit the same bin are serialised by the LDS, not by instructions).
+__device__ __forceinline__ void digit_count(bool valid, uint32_t d, uint32_t* cnt)
 {
-    uint64_t peers = __ballot(valid);
-    for (uint32_t bit = 0; bit < bits; ++bit) {
-        const bool set = (d >> bit) & 1u;
-        const uint64_t bb = __ballot(set);
-        peers &= set ? bb : ~bb;
-    }
-    const uint64_t lt = (1ull << lane_id()) - 1ull;
-    if (valid && (peers & lt) == 0) atomicAdd(&cnt[d], (uint32_t)__popcll(peers));
+    if (valid) atomicAdd(&cnt[d], 1u);
 }
 
 // Block-wide exclusive scan of one value per thread (blockDim.x a multiple of 64).  `lds` must

@@ -133,7 +133,7 @@ __global__ __launch_bounds__(kHistThreads) void k_predict(Batch b)
             G.w[i] = (k == G.C) ? 0.0f : G.p_s * w[it];
             G.key[i] = k;
         }
-        wave_digit_count(valid, (k >> shift) & (nbins - 1u), bits, cnt);
+        digit_count(valid, (k >> shift) & (nbins - 1u), cnt);
     }
     __syncthreads();
     for (uint32_t d = threadIdx.x; d < nbins; d += kHistThreads)

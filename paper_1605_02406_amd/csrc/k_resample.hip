@@ -57,10 +57,22 @@ __global__ __launch_bounds__(kResThreads) void k_resample(Batch b)
     const int lane = lane_id();
     const int wave = threadIdx.x / kWave;
 
-    // joint weight before this tile and in total, from the partial sums of the persistent tiles
-    // (kResTile particles each) and of the new-born tiles (kBornTile slots each)
     const bool born = tile >= G.n_res_ptiles;
     const uint32_t t_local = born ? tile - G.n_res_ptiles : tile;
+    const uint32_t n_src = born ? G.nb : nu;
+    const uint32_t wbase = t_local * kResTile + wave * kSrc;
+
+    // this wave's weights first, so their loads overlap the prefix below
+    const float* wsrc = born ? G.bw : G.sw;
+    float wl[kResRounds];
+#pragma unroll
+    for (int r = 0; r < kResRounds; ++r) {
+        const uint32_t i = wbase + r * kWave + lane;
+        wl[r] = i < n_src ? wsrc[i] : 0.0f;
+    }
+
+    // joint weight before this tile and in total, from the partial sums of the persistent tiles
+    // (kResTile particles each) and of the new-born tiles (kBornTile slots each)
     const uint32_t nparts = G.n_res_ptiles + G.n_born_parts;
     const uint32_t limit = born ? G.n_res_ptiles + t_local * (kResTile / kBornTile) : tile;
     uint64_t before = 0, all = 0;
@@ -81,9 +93,6 @@ __global__ __launch_bounds__(kResThreads) void k_resample(Batch b)
     const uint64_t W = block_sum(all, tmp);
     if (tile == 0 && threadIdx.x == 0) *G.W_fixed = W;
 
-    const uint32_t n_src = born ? G.nb : nu;
-    const uint32_t wbase = t_local * kResTile + wave * kSrc;
-
     if (W == 0) {  // nothing carries weight: keep the sorted persistent set as it is
         if (!born) {
             for (int r = 0; r < kResRounds; ++r) {
@@ -100,13 +109,11 @@ __global__ __launch_bounds__(kResThreads) void k_resample(Batch b)
         return;
     }
 
-    const float* wsrc = born ? G.bw : G.sw;
     uint64_t q[kResRounds];
     uint64_t wsum = 0;
 #pragma unroll
     for (int r = 0; r < kResRounds; ++r) {
-        const uint32_t i = wbase + r * kWave + lane;
-        q[r] = i < n_src ? fixed40(wsrc[i]) : 0;
+        q[r] = fixed40(wl[r]);
         wsum += q[r];
     }
     wsum = wave_sum(wsum);
@@ -155,13 +162,34 @@ __global__ __launch_bounds__(kResThreads) void k_resample(Batch b)
         // the map is written and read by this wave only
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
         __builtin_amdgcn_wave_barrier();
-        for (uint32_t j = wb + lane; j < we; j += kWave) {
-            const uint32_t i = wbase + map[j - wb];
-            G.x[j] = px[i];
-            G.y[j] = py[i];
-            G.vx[j] = pvx[i];
-            G.vy[j] = pvy[i];
-            G.w[j] = out_w;
+        // four outputs per lane per step, their source reads issued together
+        constexpr int kUnroll = 4;
+        for (uint32_t j0s = wb + lane; j0s < we; j0s += kUnroll * kWave) {
+            uint32_t src[kUnroll];
+            float ox[kUnroll], oy[kUnroll], ovx[kUnroll], ovy[kUnroll];
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                const uint32_t j = j0s + u * kWave;
+                src[u] = j < we ? wbase + map[j - wb] : wbase;
+            }
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                ox[u] = px[src[u]];
+                oy[u] = py[src[u]];
+                ovx[u] = pvx[src[u]];
+                ovy[u] = pvy[src[u]];
+            }
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                const uint32_t j = j0s + u * kWave;
+                if (j < we) {
+                    G.x[j] = ox[u];
+                    G.y[j] = oy[u];
+                    G.vx[j] = ovx[u];
+                    G.vy[j] = ovy[u];
+                    G.w[j] = out_w;
+                }
+            }
         }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
         __builtin_amdgcn_wave_barrier();

@@ -1,19 +1,18 @@
 // Alg. 2, first line: stable sort of the particles by cell key.
 //
 // LSD radix sort over digits of at most kSortBits bits (two passes for grids up to 2^20 cells);
-// each pass moves only the key and the source index.  A pass is three kernels that communicate
-// only through memory: the digit histogram of every tile (for the first pass it comes from the
-// prediction kernel), a scan of each digit's row of tile counts, and the scatter.  No block
-// waits for another.  A last kernel gathers the FP32 particle state into sorted order through
-// the permutation; the particles arrive from the resampling nearly in cell order, so the
-// permutation mostly ascends and the gather reads whole cache lines.
+// each pass moves the key, the source index and the FP32 particle state.  A pass is three
+// kernels that communicate only through memory: the digit histogram of every tile (for the
+// first pass it comes from the prediction kernel), a scan of each digit's row of tile counts,
+// and the scatter.  No block waits for another.  A last kernel marks where each cell's run of
+// sorted particles starts and ends.
 //
-// Stable ranking inside a tile: each wave owns a contiguous quarter of the tile (1024 keys) and
-// walks it 64 keys at a time; lanes holding the same digit find each other with one ballot per
-// digit bit, take their rank from the mask of lower peers, and the lowest peer advances the
-// wave's running count of that digit.  Quarters are stacked in wave order, so every key's rank
-// is its position among equal digits in input order.  The tile is then rearranged in LDS so
-// each digit's run leaves as one contiguous block.
+// Stable ranking inside a tile: each of the block's 16 waves owns a contiguous sixteenth of the
+// tile (256 keys) and walks it 64 keys at a time; lanes holding the same digit find each other
+// with one ballot per digit bit, take their rank from the mask of lower peers, and the lowest
+// peer advances the wave's running count of that digit (16-bit counters in LDS).  Sixteenths are
+// stacked in wave order, so every key's rank is its position among equal digits in input order.
+// The tile is then rearranged in LDS so each digit's run leaves as one contiguous block.
 #include "launch.h"
 
 namespace dogm {
@@ -23,27 +22,34 @@ constexpr int kSortWaves = kSortThreads / kWave;
 struct SortArrays {
     const uint32_t* ik;
     const uint32_t* iv;  // null: the source index is the element index
+    const float *ix, *iy, *ivx, *ivy, *iw;
     uint32_t *ok, *ov;
+    float *ox, *oy, *ovx, *ovy, *ow;
 };
 
-// Pass p of P reads the predicted keys (p == 0) or the previous pass's output and writes the
-// sorted keys and permutation on the last pass; the passes alternate between the sorted and
-// the temporary arrays so that the last one lands in the sorted arrays.
+// Pass p of P reads the predicted state (p == 0) or the previous pass's output and writes the
+// sorted arrays on the last pass; the passes alternate between the sorted and the temporary
+// arrays so that the last one lands in the sorted arrays.
 __device__ __forceinline__ SortArrays sort_arrays(const GridDev& G, uint32_t pass)
 {
     const bool dst_sorted = ((G.passes - 1 - pass) & 1u) == 0;
     SortArrays a;
     if (pass == 0) {
         a.ik = G.key; a.iv = nullptr;
+        a.ix = G.x; a.iy = G.y; a.ivx = G.vx; a.ivy = G.vy; a.iw = G.w;
     } else if (dst_sorted) {
         a.ik = G.tkey; a.iv = G.tval;
+        a.ix = G.tx; a.iy = G.ty; a.ivx = G.tvx; a.ivy = G.tvy; a.iw = G.tw;
     } else {
         a.ik = G.skey; a.iv = G.perm;
+        a.ix = G.sx; a.iy = G.sy; a.ivx = G.svx; a.ivy = G.svy; a.iw = G.sw;
     }
     if (dst_sorted) {
         a.ok = G.skey; a.ov = G.perm;
+        a.ox = G.sx; a.oy = G.sy; a.ovx = G.svx; a.ovy = G.svy; a.ow = G.sw;
     } else {
         a.ok = G.tkey; a.ov = G.tval;
+        a.ox = G.tx; a.oy = G.ty; a.ovx = G.tvx; a.ovy = G.tvy; a.ow = G.tw;
     }
     return a;
 }
@@ -73,7 +79,7 @@ __global__ __launch_bounds__(kHistThreads) void k_sort_hist(Batch b, uint32_t pa
 #pragma unroll
     for (int it = 0; it < kHistItems; ++it) {
         const uint32_t i = tile * kHistTile + it * kHistThreads + threadIdx.x;
-        wave_digit_count(i < G.nu, (k[it] >> shift) & (nbins - 1u), bits, cnt);
+        digit_count(i < G.nu, (k[it] >> shift) & (nbins - 1u), cnt);
     }
     __syncthreads();
     for (uint32_t d = threadIdx.x; d < nbins; d += kHistThreads)
@@ -112,6 +118,17 @@ __global__ __launch_bounds__(kScanRowThreads) void k_scan_rows(Batch b, uint32_t
     if (threadIdx.x == 0) G.rowtot[d] = carry;
 }
 
+// Reads one state array for a wave's items (coalesced, zeros past the end).
+__device__ __forceinline__ void load_items(const float* in, uint32_t base, uint32_t n,
+                                           float (&out)[kSortItems])
+{
+#pragma unroll
+    for (int it = 0; it < kSortItems; ++it) {
+        const uint32_t idx = base + it * kWave + lane_id();
+        out[it] = idx < n ? in[idx] : 0.0f;
+    }
+}
+
 // Writes one payload array in destination order: every element goes to its local sorted slot in
 // LDS, then each thread moves the slots it owns to their global positions.
 template <typename T>
@@ -145,13 +162,14 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(Batch b, uint32_t
     const int lane = lane_id();
     const uint64_t lt_mask = (1ull << lane) - 1ull;
 
-    // LDS: per-wave digit counts, local digit starts, global digit offsets, one staging row
-    uint32_t* cnt = lds;                          // [kSortWaves][nbins]
-    uint32_t* tstart = cnt + kSortWaves * nbins;  // [nbins]
-    uint32_t* goff = tstart + nbins;              // [nbins]
-    uint32_t* stage = goff + nbins;               // [kSortTile]
+    // LDS: per-wave digit counts (16-bit: at most kSortTile per digit), local digit starts,
+    // global digit offsets, one staging row
+    uint16_t* cnt = reinterpret_cast<uint16_t*>(lds);       // [kSortWaves][nbins]
+    uint32_t* tstart = lds + (kSortWaves * nbins) / 2;      // [nbins]
+    uint32_t* goff = tstart + nbins;                        // [nbins]
+    uint32_t* stage = goff + nbins;                         // [kSortTile]
 
-    for (uint32_t d = threadIdx.x; d < kSortWaves * nbins; d += kSortThreads) cnt[d] = 0;
+    for (uint32_t d = threadIdx.x; d < (kSortWaves * nbins) / 2; d += kSortThreads) lds[d] = 0;
     __syncthreads();
 
     const SortArrays A = sort_arrays(G, pass);
@@ -164,6 +182,9 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(Batch b, uint32_t
         k[it] = valid ? A.ik[idx] : 0u;
         v[it] = valid ? (A.iv ? A.iv[idx] : idx) : 0u;
     }
+    // the first state array is read while the tile is ranked
+    float pa[kSortItems], pb[kSortItems];
+    load_items(A.ix, base, G.nu, pa);
     // stable ranks inside the wave's quarter
 #pragma unroll
     for (int it = 0; it < kSortItems; ++it) {
@@ -179,7 +200,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(Batch b, uint32_t
         const uint32_t below = (uint32_t)__popcll(peers & lt_mask);
         uint32_t before = 0;
         if (valid) before = cnt[wave * nbins + d];
-        if (valid && below == 0) cnt[wave * nbins + d] = before + (uint32_t)__popcll(peers);
+        if (valid && below == 0) cnt[wave * nbins + d] = (uint16_t)(before + (uint32_t)__popcll(peers));
         rank[it] = valid ? before + below : 0xFFFFFFFFu;
     }
     __syncthreads();
@@ -201,7 +222,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(Batch b, uint32_t
             uint32_t acc = 0;
             for (int w = 0; w < kSortWaves; ++w) {
                 const uint32_t c = cnt[w * nbins + d];
-                cnt[w * nbins + d] = acc;
+                cnt[w * nbins + d] = (uint16_t)acc;
                 acc += c;
             }
             tot[j] = acc;
@@ -257,52 +278,37 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(Batch b, uint32_t
             }
         }
     }
-    // the source indices through the same LDS row
+    // the source index and the state, one array at a time through the same LDS row; the next
+    // array's loads are in flight while the current one is staged
     move_out(v, A.ov, stage, lpos, gpos);
+    load_items(A.iy, base, G.nu, pb);
+    move_out(pa, A.ox, stage, lpos, gpos);
+    load_items(A.ivx, base, G.nu, pa);
+    move_out(pb, A.oy, stage, lpos, gpos);
+    load_items(A.ivy, base, G.nu, pb);
+    move_out(pa, A.ovx, stage, lpos, gpos);
+    load_items(A.iw, base, G.nu, pa);
+    move_out(pb, A.ovy, stage, lpos, gpos);
+    move_out(pa, A.ow, stage, lpos, gpos);
 }
 
-// The particle state in sorted order, s*[i] = *[perm[i]], and the particle range of every cell
-// (its first and one-past-last sorted position; the prediction cleared them, so empty cells keep
-// start == end).
-constexpr int kGatherItems = 4;
+// The particle range of every cell: its first and one-past-last sorted position (the
+// prediction cleared them, so empty cells keep start == end).
+constexpr int kRangeItems = 4;
 
-__global__ __launch_bounds__(kElemThreads) void k_sort_gather(Batch b)
+__global__ __launch_bounds__(kElemThreads) void k_cell_ranges(Batch b)
 {
     const int gi = batch_grid(b);
     const GridDev& G = *b.g[gi];
     const uint32_t tile = xcd_tile(b, gi);
-    uint32_t src[kGatherItems];
 #pragma unroll
-    for (int it = 0; it < kGatherItems; ++it) {
-        const uint32_t i = (tile * kGatherItems + it) * kElemThreads + threadIdx.x;
-        src[it] = i < G.nu ? G.perm[i] : 0u;
-    }
-    float x[kGatherItems], y[kGatherItems], vx[kGatherItems], vy[kGatherItems], w[kGatherItems];
-#pragma unroll
-    for (int it = 0; it < kGatherItems; ++it) {
-        const uint32_t i = (tile * kGatherItems + it) * kElemThreads + threadIdx.x;
-        const bool ok = i < G.nu;
-        x[it] = ok ? G.x[src[it]] : 0.0f;
-        y[it] = ok ? G.y[src[it]] : 0.0f;
-        vx[it] = ok ? G.vx[src[it]] : 0.0f;
-        vy[it] = ok ? G.vy[src[it]] : 0.0f;
-        w[it] = ok ? G.w[src[it]] : 0.0f;
-    }
-#pragma unroll
-    for (int it = 0; it < kGatherItems; ++it) {
-        const uint32_t i = (tile * kGatherItems + it) * kElemThreads + threadIdx.x;
-        if (i < G.nu) {
-            G.sx[i] = x[it];
-            G.sy[i] = y[it];
-            G.svx[i] = vx[it];
-            G.svy[i] = vy[it];
-            G.sw[i] = w[it];
-            const uint32_t k = G.skey[i];
-            if (k < G.C) {
-                if (i == 0 || G.skey[i - 1] != k) G.cstart[k] = i;
-                if (i + 1 == G.nu || G.skey[i + 1] != k) G.cend[k] = i + 1;
-            }
-        }
+    for (int it = 0; it < kRangeItems; ++it) {
+        const uint32_t i = (tile * kRangeItems + it) * kElemThreads + threadIdx.x;
+        if (i >= G.nu) continue;
+        const uint32_t k = G.skey[i];
+        if (k >= G.C) continue;
+        if (i == 0 || G.skey[i - 1] != k) G.cstart[k] = i;
+        if (i + 1 == G.nu || G.skey[i + 1] != k) G.cend[k] = i + 1;
     }
 }
 
@@ -341,15 +347,15 @@ hipError_t launch_sort(const GridRef* g, int n, hipStream_t s)
         const uint32_t tiles =
             make_batch(b, sub, m, [](const GridDev& G) { return xcd_blocks(G.n_sort_tiles); });
         const uint32_t nbins = 1u << maxbits;
-        const size_t lds =
-            sizeof(uint32_t) * ((size_t)kSortWaves * nbins + 2 * nbins + kSortTile);
+        const size_t lds = sizeof(uint16_t) * (size_t)kSortWaves * nbins +
+                           sizeof(uint32_t) * (2 * (size_t)nbins + kSortTile);
         if (tiles) DOGM_LAUNCH(k_sort_scatter, dim3(tiles), dim3(kSortThreads), lds, s, b, pass);
     }
     Batch b;
     const uint32_t blocks = make_batch(b, g, n, [](const GridDev& G) {
-        return xcd_blocks(ceil_div(G.nu, kGatherItems * kElemThreads));
+        return xcd_blocks(ceil_div(G.nu, kRangeItems * kElemThreads));
     });
-    if (blocks) DOGM_LAUNCH(k_sort_gather, dim3(blocks), dim3(kElemThreads), 0, s, b);
+    if (blocks) DOGM_LAUNCH(k_cell_ranges, dim3(blocks), dim3(kElemThreads), 0, s, b);
     return hipGetLastError();
 }
 
