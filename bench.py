@@ -6,7 +6,8 @@ at 0.2 m with 2^21 persistent and 2^18 new-born particles over a synthetic ray-c
 (30 moving boxes, 1 % static clutter).  Measurement grids are generated and uploaded before the
 timed region.  Prints one JSON line.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--cpu-cycles N] [--copy-calibration]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--cpu-seconds S] [--copy-calibration]
+    python bench.py --traffic-from FETCH.csv WRITE.csv --traffic-command CMD ...
 
 The timed region replays K cycles captured as HIP graphs (one graph per cycle, each with its own
 measurement grid), so host launch overhead is out of the loop; the same K cycles stepped call by
@@ -109,18 +110,86 @@ def source_digest(kernel: str) -> str:
     return h.hexdigest()
 
 
+def traffic_path(workload: str) -> str:
+    return os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+
+
 def measured_traffic(kernel: str, workload: str):
     """HBM bytes per launch from the committed counter summary, or None if there is none or
     the kernel's source changed since the counters were taken."""
-    safe = kernel.replace("<", "_").replace(">", "")
-    path = os.path.join(ROOT, "profiles", f"traffic_{safe}_{workload}.json")
+    path = traffic_path(workload)
     if not os.path.exists(path):
         return None
     with open(path) as fh:
-        rec = json.load(fh)
-    if rec.get("source_sha256") != source_digest(kernel):
+        rec = json.load(fh).get("kernels", {}).get(kernel)
+    if not rec or rec.get("source_sha256") != source_digest(kernel):
         return None
     return rec.get("hbm_bytes_per_launch")
+
+
+def short_name(full: str) -> str:
+    """Kernel name as the trace hook reports it, from the demangled name in a counter file."""
+    name = full.split("(")[0].replace("void ", "").replace("dogm::", "").strip()
+    return name
+
+
+def write_traffic(fetch_csv: str, write_csv: str, workload: str, commands):
+    """Turns two rocprofv3 counter passes (FETCH_SIZE, WRITE_SIZE; KiB per dispatch) into HBM
+    bytes per launch of every kernel, calibrated by the same counters on the 1 GiB device copy
+    that --copy-calibration runs, and writes the JSON record and a markdown table."""
+    import csv
+
+    def load(path, counter):
+        per = {}
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] == counter:
+                per.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+        return per
+
+    f = load(fetch_csv, "FETCH_SIZE")
+    w = load(write_csv, "WRITE_SIZE")
+    gib_kib = float(1 << 20)
+    copy_f = max(f.get("__amd_rocclr_copyBuffer", [0.0]))
+    copy_w = max(w.get("__amd_rocclr_copyBuffer", [0.0]))
+    if copy_f <= 0 or copy_w <= 0:
+        raise SystemExit("no 1 GiB calibration copy in the counter files (run with --copy-calibration)")
+    ff, wf = gib_kib / copy_f, gib_kib / copy_w
+    rec = {"workload": workload, "fetch_factor": ff, "write_factor": wf,
+           "calibration": {"copy_fetch_kib": copy_f, "copy_write_kib": copy_w,
+                           "copy_bytes": 1 << 30},
+           "commands": commands, "kernels": {}}
+    lines = [f"# HBM traffic per kernel launch, {workload}", "", "Commands (two separate counter passes):", ""]
+    lines += ["    " + c for c in commands]
+    lines += ["", f"Calibration: the 1 GiB device copy reads FETCH_SIZE = {copy_f:.0f} KiB and "
+                  f"WRITE_SIZE = {copy_w:.0f} KiB, so bytes read = {ff:.3f} x FETCH_SIZE and "
+                  f"bytes written = {wf:.3f} x WRITE_SIZE (KiB = 1024 B).", "",
+              "Mean over the launches in the run; MB = 10^6 bytes after calibration; algorithmic "
+              "bytes per launch as bench.py counts them.", "",
+              "| kernel | launches | FETCH_SIZE KiB | WRITE_SIZE KiB | read MB | written MB | "
+              "algorithmic MB | traffic / algorithmic |", "|---|---|---|---|---|---|---|---|"]
+    from paper_1605_02406_amd import scenes
+    wl = scenes.WORKLOADS[workload]
+    nu, nb, C = wl["n_pers"], wl["n_born"], wl["nx"] * wl["ny"]
+    for full in sorted(f):
+        name = short_name(full)
+        if name not in KERNEL_SOURCE or full not in w:
+            continue
+        fk = sum(f[full]) / len(f[full])
+        wk = sum(w[full]) / len(w[full])
+        rd, wr = fk * 1024 * ff, wk * 1024 * wf
+        alg = algorithmic_bytes(name, nu, nb, C)
+        rec["kernels"][name] = {"launches": len(f[full]), "fetch_kib": fk, "write_kib": wk,
+                                "read_bytes": rd, "written_bytes": wr,
+                                "hbm_bytes_per_launch": rd + wr,
+                                "algorithmic_bytes_per_launch": alg,
+                                "source_sha256": source_digest(name)}
+        lines.append(f"| `{name}` | {len(f[full])} | {fk:.0f} | {wk:.0f} | {rd / 1e6:.1f} | "
+                     f"{wr / 1e6:.1f} | {alg / 1e6:.1f} | {(rd + wr) / alg:.2f} |")
+    with open(traffic_path(workload), "w") as fh:
+        json.dump(rec, fh, indent=1)
+        fh.write("\n")
+    with open(os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}.md"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
 
 
 def parse():
@@ -129,15 +198,24 @@ def parse():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="c512")
-    ap.add_argument("--cpu-cycles", type=int, default=3,
-                    help="oracle cycles timed on the host for the CPU baseline (0: skip)")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="host time budget of the oracle's CPU baseline: whole cycles are run "
+                         "until it is spent (0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one device copy of 1 GiB (for counter calibration)")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="no GPU run: turn two rocprofv3 counter files into the traffic record")
+    ap.add_argument("--traffic-command", action="append", default=[],
+                    help="command line recorded with --traffic-from (repeat for each pass)")
     return ap.parse_args()
 
 
 def main():
     args = parse()
+    if args.traffic_from:
+        write_traffic(args.traffic_from[0], args.traffic_from[1], args.workload,
+                      args.traffic_command)
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py runs on one GPU: this build has no multi-GPU path "
@@ -292,15 +370,15 @@ def main():
         "meas_generation_s": t_gen,
     }
 
-    if args.cpu_cycles > 0:
-        print(f"[bench] oracle on the host, {args.cpu_cycles} cycles", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(p, seq, args.cpu_cycles)
+    if args.cpu_seconds > 0:
+        print(f"[bench] oracle on the host, {args.cpu_seconds:.0f} s", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(p, seq, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 
-def cpu_baseline(p, seq, n):
-    """The oracle (single-threaded FP64 C, as it stands) on the same workload: n cycles from its
-    own initial state, timed on this host."""
+def cpu_baseline(p, seq, budget_s):
+    """The oracle (single-threaded FP64 C, as it stands) on the same workload: whole cycles from
+    its own initial state until `budget_s` seconds of host time are spent, timed on this host."""
     import numpy as np
 
     import oracle
@@ -308,10 +386,14 @@ def cpu_baseline(p, seq, n):
                        p.sigma_birth_vel, p.alpha_free, p.n_pers, p.n_born, seed=p.seed)
     st = oracle.init_state(op, op.n_pers)
     m_F = np.zeros(op.C)
+    n = 0
     t0 = time.perf_counter()
-    for k in range(1, n + 1):
-        st, m_F, _ = oracle.cycle(op, k, st, m_F, seq[(k - 1) % len(seq)])
-    dt = time.perf_counter() - t0
+    while True:
+        n += 1
+        st, m_F, _ = oracle.cycle(op, n, st, m_F, seq[(n - 1) % len(seq)])
+        dt = time.perf_counter() - t0
+        if dt >= budget_s:
+            break
     return {"value": n / dt, "unit": "cycles/s", "cores": 1, "kind": "oracle",
             "sample": f"{n} cycles of the same 512x512 / 2^21+2^18 workload from the oracle's "
                       f"own initial state ({dt:.1f} s)",

@@ -207,7 +207,9 @@ int dogm_step_batch(dogm_grid* const* grids, const dogm_meas* meas, int n,
  * kernel's name, static storage.  The events, the arrays and the `kernel` string are the
  * caller's and must stay valid until dogm_trace_end, which returns the number of traced
  * launches in *count.  A trace is per thread; DOGM_EINVAL on a negative capacity or NULL
- * events with capacity > 0, DOGM_ESTATE from dogm_trace_end without an active trace. */
+ * events with capacity > 0, DOGM_ESTATE from dogm_trace_end without an active trace,
+ * DOGM_EHIP from dogm_trace_end if recording one of the events failed (the count is still
+ * written; the trace ends either way). */
 int dogm_trace_begin(void* const* events, const char** names, int capacity, const char* kernel);
 int dogm_trace_end(int* count);
 

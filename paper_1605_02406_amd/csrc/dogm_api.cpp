@@ -475,7 +475,7 @@ int dogm_trace_begin(void* const* events, const char** names, int capacity, cons
 {
     if (capacity < 0 || (capacity > 0 && !events)) return DOGM_EINVAL;
     g_trace_storage = Trace{reinterpret_cast<hipEvent_t*>(const_cast<void**>(events)), names,
-                            kernel, capacity, 0};
+                            kernel, capacity, 0, hipSuccess};
     g_trace = &g_trace_storage;
     return DOGM_OK;
 }
@@ -484,8 +484,9 @@ int dogm_trace_end(int* count)
 {
     if (!g_trace) return DOGM_ESTATE;
     if (count) *count = g_trace->n;
+    const hipError_t e = g_trace->err;
     g_trace = nullptr;
-    return DOGM_OK;
+    return e == hipSuccess ? DOGM_OK : hip_fail(e, "dogm_trace_end");
 }
 
 }  // extern "C"

@@ -61,7 +61,36 @@ static_assert(kResTile % kBornTile == 0, "a resampling tile covers whole new-bor
 
 constexpr int kElemThreads = 256;  // element-wise kernels
 
-struct GridDev {
+// The grid descriptor, over a pointer kind: the host builds and stores it with plain pointers
+// (GridDev); kernels read a private copy whose pointers are in the global address space
+// (GridView), so every array access uses the global memory instructions, which do not share
+// the wait counter of LDS operations and cross-lane shuffles, and nothing is reloaded after a
+// store.  Both kinds have the same layout.
+template <typename T>
+using HostPtr = T*;
+template <typename T>
+using GlobalPtr = __attribute__((address_space(1))) T*;
+template <typename T>
+using ConstPtr = __attribute__((address_space(4))) const T*;  // read-only while a kernel runs
+
+// A device array seen by a kernel: a global-address-space pointer whose element access forms
+// the byte offset in 32 bits (every array holds fewer than 2^30 elements of at most 8 bytes),
+// so the compiler addresses it with a scalar base and one 32-bit offset register instead of a
+// 64-bit address pair per access.  Same size and bits as a plain pointer.
+template <typename T>
+struct GArr {
+    GlobalPtr<T> p;
+    __device__ __forceinline__ __attribute__((address_space(1))) T& operator[](uint32_t i) const
+    {
+        using Byte = __attribute__((address_space(1))) unsigned char;
+        return *(GlobalPtr<T>)((Byte*)(GlobalPtr<void>)p + i * (uint32_t)sizeof(T));
+    }
+    __device__ __forceinline__ __attribute__((address_space(1))) T& operator*() const { return *p; }
+    __device__ __forceinline__ explicit operator bool() const { return p != nullptr; }
+};
+
+template <template <typename> class P>
+struct GridT {
     // parameters
     int32_t nx, ny;
     uint32_t C, nu, nb;
@@ -72,47 +101,54 @@ struct GridDev {
     uint32_t dshift[kMaxPasses], dbits[kMaxPasses];
     uint32_t n_sort_tiles, n_hist_tiles, n_cell_parts, n_res_ptiles, n_res_btiles, n_born_parts;
     // persistent particles (start of a cycle / after resampling) and their cell keys
-    float *x, *y, *vx, *vy, *w;
-    uint32_t* key;
+    P<float> x, y, vx, vy, w;
+    P<uint32_t> key;
     // particles sorted by cell
-    float *sx, *sy, *svx, *svy, *sw;
-    uint32_t *skey, *perm;
+    P<float> sx, sy, svx, svy, sw;
+    P<uint32_t> skey, perm;
     // ping-pong partner of the sorted arrays during the sort
-    float *tx, *ty, *tvx, *tvy, *tw;
-    uint32_t *tkey, *tval;
+    P<float> tx, ty, tvx, tvy, tw;
+    P<uint32_t> tkey, tval;
     // cells
-    uint32_t *cstart, *cend;
-    double *sum_w, *sum_wt;
-    double* msum;  // [5][C]: sums of w vx, w vy, w vx^2, w vy^2, w vx vy per cell
-    float *m_pO, *m_pF, *m_O, *m_F, *rho_b, *rho_p, *pign;
-    double *mu_A, *mu_UA;
-    uint32_t* born_off;
-    float *mean_x, *mean_y, *var_x, *var_y, *cov_xy;
-    uint8_t* mflag;
+    P<uint32_t> cstart, cend;
+    P<double> sum_w, sum_wt;
+    P<double> msum;  // [5][C]: sums of w vx, w vy, w vx^2, w vy^2, w vx vy per cell
+    P<float> m_pO, m_pF, m_O, m_F, rho_b, rho_p, pign;
+    P<double> mu_A, mu_UA;
+    P<uint32_t> born_off;
+    P<float> mean_x, mean_y, var_x, var_y, cov_xy;
+    P<uint8_t> mflag;
     // new-born particles
-    float *bx, *by, *bvx, *bvy, *bw;
-    uint32_t* bkey;
-    uint8_t* bassoc;
-    // per-cycle scratch: digit histograms of 1024-key sub-tiles (digit-major,
+    P<float> bx, by, bvx, bvy, bw;
+    P<uint32_t> bkey;
+    P<uint8_t> bassoc;
+    // per-cycle scratch: digit histograms of every sort tile (digit-major,
     // [kSortBins][n_hist_tiles]) with their row totals, fixed-point partial sums of new-born
     // masses (per 256 cells) and of joint weights (per persistent resampling tile, then per
     // new-born tile), the first slot of every cell with births (its cell id, kNoCell
     // elsewhere) and the cell of the first slot of every new-born tile
-    uint32_t *hist, *rowtot;
-    uint64_t *bpart, *rpart;
-    uint32_t *born_mark, *tile_first;
+    P<uint32_t> hist, rowtot;
+    P<uint64_t> bpart, rpart;
+    P<uint32_t> born_mark, tile_first;
     // device scalars: the cycle to run next (advanced by the resampling) and the cycle being
     // run (set by the prediction); every writer of either stores one and the same value
-    uint32_t* cycle;
-    uint32_t* cycle_run;
-    uint32_t* status;
-    uint64_t* W_fixed;
-    uint64_t* S_fixed;
+    P<uint32_t> cycle;
+    P<uint32_t> cycle_run;
+    P<uint32_t> status;
+    P<uint64_t> W_fixed;
+    P<uint64_t> S_fixed;
 };
+using GridDev = GridT<HostPtr>;
+using GridView = GridT<GArr>;
+static_assert(sizeof(GridDev) == sizeof(GridView), "one layout for both pointer kinds");
 
-struct MeasDev {
-    const float *m_occ, *m_free, *p_assoc, *mu_vx, *mu_vy, *var_v;
+template <template <typename> class P>
+struct MeasT {
+    P<const float> m_occ, m_free, p_assoc, mu_vx, mu_vy, var_v;
 };
+using MeasDev = MeasT<HostPtr>;
+using MeasView = MeasT<GArr>;
+static_assert(sizeof(MeasDev) == sizeof(MeasView), "one layout for both pointer kinds");
 
 struct Batch {
     int n;
@@ -120,6 +156,49 @@ struct Batch {
     const GridDev* g[kMaxBatch];
     MeasDev m[kMaxBatch];
 };
+
+// Private copies of a grid's descriptor and measurement with global-address-space pointers.
+// The descriptor is read through the constant address space (it is never written while a
+// kernel runs), so its fields arrive by scalar loads into scalar registers.
+static_assert(sizeof(GridView) % 8 == 0, "the descriptor is copied in 8-byte words");
+__device__ __forceinline__ GridView grid_view(const GridDev* p)
+{
+    const auto src = (ConstPtr<uint64_t>)(const void*)p;
+    GridView v;
+#pragma unroll
+    for (size_t i = 0; i < sizeof(GridView) / 8; ++i) {
+        const uint64_t word = src[i];
+        __builtin_memcpy(reinterpret_cast<char*>(&v) + 8 * i, &word, 8);
+    }
+    return v;
+}
+
+// Digit position and width of sort pass `pass` (read from the descriptor in memory: indexing
+// the private copy with a run-time pass number would place it in scratch).
+__device__ __forceinline__ uint32_t pass_shift(const GridDev* p, uint32_t pass)
+{
+    return ((ConstPtr<GridDev>)(const void*)p)->dshift[pass];
+}
+__device__ __forceinline__ uint32_t pass_bits(const GridDev* p, uint32_t pass)
+{
+    return ((ConstPtr<GridDev>)(const void*)p)->dbits[pass];
+}
+__device__ __forceinline__ MeasView meas_view(const MeasDev& m)
+{
+    MeasView v;
+    __builtin_memcpy(&v, (const void*)&m, sizeof(v));
+    return v;
+}
+
+// Sets status bits of a grid (a device-wide atomic OR; rare events only).
+__device__ __forceinline__ void status_or(const GridView& G, uint32_t bits)
+{
+    atomicOr((uint32_t*)G.status.p, bits);
+}
+__device__ __forceinline__ void status_or(const GridDev& G, uint32_t bits)
+{
+    atomicOr(G.status, bits);
+}
 
 // Grid of this block and the block's index within the grid.
 __device__ __forceinline__ int batch_grid(const Batch& b)
@@ -169,7 +248,7 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 ctr, uint32_t key_lo, uint3
     return make_uint4(a, b, c, d);
 }
 
-__device__ __forceinline__ uint4 draw(const GridDev& G, uint32_t index, uint32_t cycle,
+__device__ __forceinline__ uint4 draw(const GridView& G, uint32_t index, uint32_t cycle,
                                       uint32_t purpose)
 {
     return philox4x32_10(make_uint4(index, cycle, purpose, G.grid_id), G.seed_lo, G.seed_hi);
@@ -194,7 +273,7 @@ __device__ __forceinline__ void box_muller_f32(float u1, float u2, float& n1, fl
 }
 
 // Cell of an FP32 position: one correctly rounded FP32 division per axis, C outside the grid.
-__device__ __forceinline__ uint32_t cell_of(const GridDev& G, float x, float y)
+__device__ __forceinline__ uint32_t cell_of(const GridView& G, float x, float y)
 {
     const float fx = x / G.r;
     const float fy = y / G.r;

@@ -1,6 +1,6 @@
-// Per-cell work over the sorted particles: the particle range of every cell (Alg. 2), the
-// Dempster-Shafer cell update with the new-born split (Alg. 3), the normalisation components of
-// the persistent update (Alg. 4) and the velocity moments (Alg. 6).
+// Per-cell work over the sorted particles and the cell ranges that the sort recorded (Alg. 2):
+// the Dempster-Shafer cell update with the new-born split (Alg. 3), the normalisation components
+// of the persistent update (Alg. 4) and the velocity moments (Alg. 6).
 //
 // Two passes.  The first is particle-parallel: per-cell sums are segmented reductions over the
 // sorted particles instead of the paper's prefix-sum differences (a global FP32 prefix loses the
@@ -30,7 +30,7 @@ constexpr uint32_t kNone = 0xFFFFFFFFu;
 // The cell ranges recorded by the sort decide where the wave starts (after the cell that began
 // before its share) and ends (with the cell that holds its last particle).
 template <int NV, typename Val, typename Emit>
-__device__ __forceinline__ void seg_reduce(const GridDev& G, uint32_t wave_index, Val val,
+__device__ __forceinline__ void seg_reduce(const GridView& G, uint32_t wave_index, Val val,
                                            Emit emit)
 {
     const int lane = lane_id();
@@ -38,11 +38,29 @@ __device__ __forceinline__ void seg_reduce(const GridDev& G, uint32_t wave_index
     const uint32_t a = wave_index * kSegRange;
     if (a >= n) return;
     const uint32_t b = min(a + (uint32_t)kSegRange, n);
+
+    // chunks of kSegRange particles at fixed offsets from a; the first chunk is read while the
+    // wave's range is looked up (particles before p0 or past pend are masked out below)
+    uint32_t key[kSegItems];
+    float pw[kSegItems], pvx[kSegItems], pvy[kSegItems];
+    auto load_chunk = [&](uint32_t base, uint32_t bound) {
+        const uint32_t i0 = base + lane * kSegItems;
+#pragma unroll
+        for (int it = 0; it < kSegItems; ++it) {
+            const uint32_t i = i0 + it;
+            key[it] = (i < bound) ? G.skey[i] : kNone;
+            pw[it] = (i < bound) ? G.sw[i] : 0.0f;
+            pvx[it] = (i < bound) ? G.svx[i] : 0.0f;
+            pvy[it] = (i < bound) ? G.svy[i] : 0.0f;
+        }
+    };
+    load_chunk(a, b);
     const uint32_t ka = G.skey[a];
-    if (ka >= C) return;  // only particles outside the grid from here on
-    const uint32_t p0 = (a > 0 && G.skey[a - 1] == ka) ? G.cend[ka] : a;
-    if (p0 >= b) return;
+    const uint32_t kprev = a > 0 ? G.skey[a - 1] : kNone;
     const uint32_t kl = G.skey[b - 1];
+    if (ka >= C) return;  // only particles outside the grid from here on
+    const uint32_t p0 = (kprev == ka) ? G.cend[ka] : a;
+    if (p0 >= b) return;
     const uint32_t pend = kl < C ? G.cend[kl] : b;
 
     double carry[NV];
@@ -50,24 +68,13 @@ __device__ __forceinline__ void seg_reduce(const GridDev& G, uint32_t wave_index
     for (int j = 0; j < NV; ++j) carry[j] = 0.0;
     uint32_t carry_key = kNone;
 
-    for (uint32_t base = p0; base < pend; base += kSegRange) {
-        // this lane's run of kSegItems particles: loads first
+    for (uint32_t base = a; base < pend; base += kSegRange) {
+        if (base != a) load_chunk(base, pend);
         const uint32_t i0 = base + lane * kSegItems;
-        uint32_t key[kSegItems];
-        float pw[kSegItems], pvx[kSegItems], pvy[kSegItems];
 #pragma unroll
         for (int it = 0; it < kSegItems; ++it) {
             const uint32_t i = i0 + it;
-            const uint32_t k = (i < pend) ? G.skey[i] : kNone;
-            key[it] = k >= C ? kNone : k;
-        }
-#pragma unroll
-        for (int it = 0; it < kSegItems; ++it) {
-            const uint32_t i = i0 + it;
-            const bool ok = key[it] != kNone;
-            pw[it] = ok ? G.sw[i] : 0.0f;
-            pvx[it] = ok ? G.svx[i] : 0.0f;
-            pvy[it] = ok ? G.svy[i] : 0.0f;
+            if (i < p0 || i >= pend || key[it] >= C) key[it] = kNone;
         }
         const uint32_t first = key[0];
         uint32_t cur = key[0];
@@ -163,7 +170,7 @@ __device__ __forceinline__ double likelihood(double vx, double vy, double mx, do
 // (DS_resulting_masses1/2), new-born mass only where m_z(O) > 0) and the normalisation
 // components (eqs. (DSnormalizationfactor), (DSnormalizationfactor2)).  s = sum of predicted
 // weights, st = sum of g w.  Returns rho_p; *rb_out gets the stored rho_b.
-__device__ __forceinline__ double cell_update(const GridDev& G, const MeasDev& M, uint32_t c,
+__device__ __forceinline__ double cell_update(const GridView& G, const MeasView& M, uint32_t c,
                                               double s, double st, float* rb_out)
 {
     const double po = s < 1.0 ? s : 1.0;
@@ -201,14 +208,14 @@ __device__ __forceinline__ double cell_update(const GridDev& G, const MeasDev& M
     G.pign[c] = (float)(o + 0.5 * (1.0 - o - f));
     G.mu_UA[c] = s > 0.0 ? rp / s : 0.0;
     G.mu_A[c] = st > 0.0 ? rp / st : 0.0;
-    if (st_bits) atomicOr(G.status, st_bits);
+    if (st_bits) status_or(G, st_bits);
     *rb_out = (float)rb;
     return rp;
 }
 
 // Moments are defined where the stored rho_p is positive and the cell holds particles (the
 // caller decides); sums over weights that are all zero give zero moments.
-__device__ __forceinline__ void write_moments(const GridDev& G, uint32_t c, bool defined,
+__device__ __forceinline__ void write_moments(const GridView& G, uint32_t c, bool defined,
                                               double norm, double sx, double sy, double sxx,
                                               double syy, double sxy)
 {
@@ -236,8 +243,8 @@ template <bool kAssoc>
 __global__ __launch_bounds__(kSegThreads) void k_seg_sums(Batch b)
 {
     const int gi = batch_grid(b);
-    const GridDev& G = *b.g[gi];
-    const MeasDev& M = b.m[gi];
+    const GridView G = grid_view(b.g[gi]);
+    const MeasView M = meas_view(b.m[gi]);
     const uint32_t tile = xcd_tile(b, gi);
     const uint32_t wave = tile * (kSegThreads / kWave) + threadIdx.x / kWave;
     if (kAssoc) {
@@ -282,8 +289,8 @@ __global__ __launch_bounds__(kCellThreads) void k_cells(Batch b)
 {
     __shared__ uint64_t tmp[kCellThreads / kWave + 1];
     const int gi = batch_grid(b);
-    const GridDev& G = *b.g[gi];
-    const MeasDev& M = b.m[gi];
+    const GridView G = grid_view(b.g[gi]);
+    const MeasView M = meas_view(b.m[gi]);
     const uint32_t part = blockIdx.x - b.bstart[gi];
     const uint32_t c = part * kCellThreads + threadIdx.x;
     uint64_t q = 0;
@@ -352,7 +359,7 @@ hipError_t launch_update(const GridRef* g, int n, hipStream_t s)
 __global__ __launch_bounds__(kSegThreads) void k_seg_moments(Batch b)
 {
     const int gi = batch_grid(b);
-    const GridDev& G = *b.g[gi];
+    const GridView G = grid_view(b.g[gi]);
     const uint32_t tile = xcd_tile(b, gi);
     const uint32_t wave = tile * (kSegThreads / kWave) + threadIdx.x / kWave;
     seg_reduce<5>(

@@ -20,7 +20,7 @@ hipError_t launch_write_desc(const GridDev& hd, GridDev* dd, hipStream_t s)
 __global__ __launch_bounds__(kElemThreads) void k_init(Batch b)
 {
     const int gi = batch_grid(b);
-    const GridDev& G = *b.g[gi];
+    const GridView G = grid_view(b.g[gi]);
     const uint32_t i = (blockIdx.x - b.bstart[gi]) * kElemThreads + threadIdx.x;
     if (i < G.nu) {
         const uint4 r = draw(G, i, 0u, kPurposeInit);
@@ -82,7 +82,7 @@ __global__ __launch_bounds__(kHistThreads) void k_predict(Batch b)
 {
     __shared__ uint32_t cnt[kSortBins];
     const int gi = batch_grid(b);
-    const GridDev& G = *b.g[gi];
+    const GridView G = grid_view(b.g[gi]);
     const uint32_t tile = xcd_tile(b, gi);
     if (tile >= G.n_hist_tiles) return;
     const uint32_t cycle = *G.cycle;
@@ -169,19 +169,28 @@ __global__ __launch_bounds__(kCellThreads) void k_born_offsets(Batch b)
 {
     __shared__ uint64_t tmp[kCellThreads / kWave + 1];
     const int gi = batch_grid(b);
-    const GridDev& G = *b.g[gi];
+    const GridView G = grid_view(b.g[gi]);
     const uint32_t part = blockIdx.x - b.bstart[gi];
+    const uint32_t c = part * kCellThreads + threadIdx.x;
+    const float rb = (c < G.C) ? G.rho_b[c] : 0.0f;  // read while the prefix is formed
     uint64_t before = 0, all = 0;
-    for (uint32_t t = threadIdx.x; t < G.n_cell_parts; t += kCellThreads) {
-        const uint64_t v = G.bpart[t];
-        all += v;
-        if (t < part) before += v;
+    for (uint32_t t0 = threadIdx.x; t0 < G.n_cell_parts; t0 += 4 * kCellThreads) {
+        uint64_t v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const uint32_t t = t0 + u * kCellThreads;
+            v[u] = t < G.n_cell_parts ? G.bpart[t] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            all += v[u];
+            if (t0 + u * kCellThreads < part) before += v[u];
+        }
     }
     before = block_sum(before, tmp);
     const uint64_t Stot = block_sum(all, tmp);
     if (part == 0 && threadIdx.x == 0) *G.S_fixed = Stot;
-    const uint32_t c = part * kCellThreads + threadIdx.x;
-    const uint64_t q = (c < G.C) ? fixed40(G.rho_b[c]) : 0;
+    const uint64_t q = fixed40(rb);
     uint64_t total;
     const uint64_t E = before + block_excl_scan(q, tmp, &total);
     if (c > G.C) return;
@@ -195,7 +204,7 @@ __global__ __launch_bounds__(kCellThreads) void k_born_offsets(Batch b)
             for (uint32_t t = ceil_div_dev(o, kBornTile); t * (uint32_t)kBornTile < o1; ++t)
                 G.tile_first[t] = c;
         } else {
-            atomicOr(G.status, kStNoCarrier);
+            status_or(G, kStNoCarrier);
         }
     }
 }
@@ -224,7 +233,7 @@ __device__ __forceinline__ double likelihood(double vx, double vy, double mx, do
 }
 
 // Initialises new-born slot s of cell c (born_off[c] <= s < born_off[c+1]); returns its weight.
-__device__ __forceinline__ float init_born(const GridDev& G, const MeasDev& M, uint32_t s,
+__device__ __forceinline__ float init_born(const GridView& G, const MeasView& M, uint32_t s,
                                           uint32_t c, uint32_t cycle)
 {
     const uint32_t o0 = G.born_off[c], o1 = G.born_off[c + 1];
@@ -263,8 +272,8 @@ __global__ __launch_bounds__(kResThreads) void k_particle_tiles(Batch b)
     __shared__ uint64_t tmp[kResThreads / kWave + 1];
     __shared__ uint32_t wave_last[kResThreads / kWave];
     const int gi = batch_grid(b);
-    const GridDev& G = *b.g[gi];
-    const MeasDev& M = b.m[gi];
+    const GridView G = grid_view(b.g[gi]);
+    const MeasView M = meas_view(b.m[gi]);
     const uint32_t tile = blockIdx.x - b.bstart[gi];
     const int lane = lane_id(), wave = threadIdx.x / kWave;
     uint64_t q = 0;
@@ -277,7 +286,7 @@ __global__ __launch_bounds__(kResThreads) void k_particle_tiles(Batch b)
             k[it] = i < G.nu ? G.skey[i] : kNoCell;
             w[it] = i < G.nu ? G.sw[i] : 0.0f;
         }
-        const bool assoc = M.p_assoc != nullptr;
+        const bool assoc = static_cast<bool>(M.p_assoc);
 #pragma unroll
         for (int it = 0; it < kResItems; ++it) {
             const uint32_t i = tile * kResTile + it * kResThreads + threadIdx.x;

@@ -42,10 +42,10 @@ __global__ __launch_bounds__(kResThreads) void k_resample(Batch b)
     constexpr int kSrc = kResRounds * kWave;  // sources per wave
     static_assert(kSrc <= 65536, "local source indices are 16-bit");
     __shared__ uint64_t tmp[kResWaves + 1];
-    __shared__ uint64_t wave_tot[kResWaves];
+    __shared__ uint64_t wave_tot[kResWaves];  // each wave's weight total
     __shared__ uint16_t srcmap[kResWaves][kResWindow];
     const int gi = batch_grid(b);
-    const GridDev& G = *b.g[gi];
+    const GridView G = grid_view(b.g[gi]);
     const uint32_t ntiles = G.n_res_ptiles + G.n_res_btiles;
     const uint32_t tile = xcd_tile(b, gi);
     if (tile >= ntiles) return;
@@ -62,12 +62,14 @@ __global__ __launch_bounds__(kResThreads) void k_resample(Batch b)
     const uint32_t n_src = born ? G.nb : nu;
     const uint32_t wbase = t_local * kResTile + wave * kSrc;
 
-    // this wave's weights first, so their loads overlap the prefix below
-    const float* wsrc = born ? G.bw : G.sw;
+    // each lane owns kResRounds consecutive sources; this wave's weights are read first so
+    // their loads overlap the prefix below
+    const uint32_t lbase = wbase + lane * kResRounds;
+    const auto wsrc = born ? G.bw : G.sw;
     float wl[kResRounds];
 #pragma unroll
     for (int r = 0; r < kResRounds; ++r) {
-        const uint32_t i = wbase + r * kWave + lane;
+        const uint32_t i = lbase + r;
         wl[r] = i < n_src ? wsrc[i] : 0.0f;
     }
 
@@ -110,46 +112,44 @@ __global__ __launch_bounds__(kResThreads) void k_resample(Batch b)
     }
 
     uint64_t q[kResRounds];
-    uint64_t wsum = 0;
+    uint64_t lsum = 0;
 #pragma unroll
     for (int r = 0; r < kResRounds; ++r) {
         q[r] = fixed40(wl[r]);
-        wsum += q[r];
+        lsum += q[r];
     }
-    wsum = wave_sum(wsum);
-    if (lane == 0) wave_tot[wave] = wsum;
+    const uint64_t lincl = wave_incl_scan(lsum);
+    if (lane == kWave - 1) wave_tot[wave] = lincl;
     __syncthreads();
     uint64_t run = before;
     for (int w2 = 0; w2 < wave; ++w2) run += wave_tot[w2];
+    const uint64_t wave_end = run + wave_tot[wave];
 
     const double U = (double)unit_f32(draw(G, 0u, cycle, kPurposeResample).x);
     const double spacing = __ddiv_rn((double)W, (double)nu);
     const double inv_spacing = 1.0 / spacing;
     const float out_w = (float)((double)W * 0x1p-40 / (double)nu);
 
-    // draws [j0, j1) of every source of this wave (local source r * 64 + lane); they tile the
+    // draws [j0, j1) of this lane's sources (local index lane * kResRounds + r); they tile the
     // wave's range [j_begin, j_end) in source order
     uint32_t j0[kResRounds], j1[kResRounds];
+    uint64_t F = run + lincl - lsum;
 #pragma unroll
     for (int r = 0; r < kResRounds; ++r) {
-        const uint64_t incl = wave_incl_scan(q[r]);
-        const uint64_t F_lo = run + incl - q[r];
-        run += __shfl(incl, kWave - 1, kWave);
-        j0[r] = first_draw_at(F_lo, U, spacing, inv_spacing, nu);
+        j0[r] = first_draw_at(F, U, spacing, inv_spacing, nu);
+        F += q[r];
     }
-    const uint32_t j_end = first_draw_at(run, U, spacing, inv_spacing, nu);
+    const uint32_t j_end = first_draw_at(wave_end, U, spacing, inv_spacing, nu);
+    const uint32_t next_lane = __shfl_down(j0[0], 1, kWave);
 #pragma unroll
-    for (int r = 0; r < kResRounds; ++r) {
-        const uint32_t next_lane = __shfl_down(j0[r], 1, kWave);
-        const uint32_t next_round = (r + 1 < kResRounds) ? __shfl(j0[r + 1 < kResRounds ? r + 1 : r], 0, kWave) : j_end;
-        j1[r] = lane < kWave - 1 ? next_lane : next_round;
-    }
+    for (int r = 0; r < kResRounds - 1; ++r) j1[r] = j0[r + 1];
+    j1[kResRounds - 1] = lane < kWave - 1 ? next_lane : j_end;
     const uint32_t j_begin = __shfl(j0[0], 0, kWave);
 
-    const float* px = born ? G.bx : G.sx;
-    const float* py = born ? G.by : G.sy;
-    const float* pvx = born ? G.bvx : G.svx;
-    const float* pvy = born ? G.bvy : G.svy;
+    const auto px = born ? G.bx : G.sx;
+    const auto py = born ? G.by : G.sy;
+    const auto pvx = born ? G.bvx : G.svx;
+    const auto pvy = born ? G.bvy : G.svy;
     uint16_t* map = srcmap[wave];
     for (uint32_t wb = j_begin; wb < j_end; wb += kResWindow) {
         const uint32_t we = min(wb + (uint32_t)kResWindow, j_end);
@@ -157,7 +157,7 @@ __global__ __launch_bounds__(kResThreads) void k_resample(Batch b)
         for (int r = 0; r < kResRounds; ++r) {
             const uint32_t lo = j0[r] > wb ? j0[r] : wb;
             const uint32_t hi = j1[r] < we ? j1[r] : we;
-            for (uint32_t j = lo; j < hi; ++j) map[j - wb] = (uint16_t)(r * kWave + lane);
+            for (uint32_t j = lo; j < hi; ++j) map[j - wb] = (uint16_t)(lane * kResRounds + r);
         }
         // the map is written and read by this wave only
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");

@@ -19,23 +19,26 @@ namespace dogm {
 
 constexpr int kSortWaves = kSortThreads / kWave;
 
+// The arrays one pass reads and writes, as raw pointers (P = HostPtr) or global-space views.
+template <template <typename> class P>
 struct SortArrays {
-    const uint32_t* ik;
-    const uint32_t* iv;  // null: the source index is the element index
-    const float *ix, *iy, *ivx, *ivy, *iw;
-    uint32_t *ok, *ov;
-    float *ox, *oy, *ovx, *ovy, *ow;
+    P<uint32_t> ik;
+    P<uint32_t> iv;  // null: the source index is the element index
+    P<float> ix, iy, ivx, ivy, iw;
+    P<uint32_t> ok, ov;
+    P<float> ox, oy, ovx, ovy, ow;
 };
 
 // Pass p of P reads the predicted state (p == 0) or the previous pass's output and writes the
 // sorted arrays on the last pass; the passes alternate between the sorted and the temporary
 // arrays so that the last one lands in the sorted arrays.
-__device__ __forceinline__ SortArrays sort_arrays(const GridDev& G, uint32_t pass)
+template <template <typename> class P>
+__device__ __forceinline__ SortArrays<P> sort_arrays(const GridT<P>& G, uint32_t pass)
 {
     const bool dst_sorted = ((G.passes - 1 - pass) & 1u) == 0;
-    SortArrays a;
+    SortArrays<P> a;
     if (pass == 0) {
-        a.ik = G.key; a.iv = nullptr;
+        a.ik = G.key; a.iv = P<uint32_t>{};
         a.ix = G.x; a.iy = G.y; a.ivx = G.vx; a.ivy = G.vy; a.iw = G.w;
     } else if (dst_sorted) {
         a.ik = G.tkey; a.iv = G.tval;
@@ -61,15 +64,16 @@ __global__ __launch_bounds__(kHistThreads) void k_sort_hist(Batch b, uint32_t pa
 {
     __shared__ uint32_t cnt[kSortBins];
     const int gi = batch_grid(b);
-    const GridDev& G = *b.g[gi];
+    const GridView G = grid_view(b.g[gi]);
     // neighbouring tiles write neighbouring words of every digit row: keep them on one XCD so
     // the partial lines meet in its L2
     const uint32_t tile = xcd_tile(b, gi);
     if (tile >= G.n_hist_tiles) return;
-    const uint32_t shift = G.dshift[pass], bits = G.dbits[pass], nbins = 1u << bits;
+    const uint32_t shift = pass_shift(b.g[gi], pass), bits = pass_bits(b.g[gi], pass);
+    const uint32_t nbins = 1u << bits;
     for (uint32_t d = threadIdx.x; d < nbins; d += kHistThreads) cnt[d] = 0;
     __syncthreads();
-    const uint32_t* keys = sort_arrays(G, pass).ik;
+    const auto keys = sort_arrays(G, pass).ik;
     uint32_t k[kHistItems];
 #pragma unroll
     for (int it = 0; it < kHistItems; ++it) {
@@ -94,9 +98,9 @@ __global__ __launch_bounds__(kScanRowThreads) void k_scan_rows(Batch b, uint32_t
 {
     __shared__ uint32_t tmp[kScanRowThreads / kWave + 1];
     const int gi = batch_grid(b);
-    const GridDev& G = *b.g[gi];
+    const GridView G = grid_view(b.g[gi]);
     const uint32_t d = blockIdx.x - b.bstart[gi];
-    uint32_t* row = G.hist + (size_t)d * G.n_hist_tiles;
+    const GArr<uint32_t> row{G.hist.p + (size_t)d * G.n_hist_tiles};
     uint32_t carry = 0;
     for (uint32_t base = 0; base < G.n_hist_tiles; base += kScanRowThreads * kRowItems) {
         const uint32_t t0 = base + threadIdx.x * kRowItems;
@@ -153,6 +157,8 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(Batch b, uint32_t
     __shared__ uint32_t scan_tmp[kSortWaves + 1];
 
     const int gi = batch_grid(b);
+    // the descriptor is read in place: a private copy of both ping-pong pointer sets costs this
+    // kernel more than the loads it saves
     const GridDev& G = *b.g[gi];
     const uint32_t tile = xcd_tile(b, gi);
     if (tile >= G.n_sort_tiles) return;
@@ -172,7 +178,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(Batch b, uint32_t
     for (uint32_t d = threadIdx.x; d < (kSortWaves * nbins) / 2; d += kSortThreads) lds[d] = 0;
     __syncthreads();
 
-    const SortArrays A = sort_arrays(G, pass);
+    const SortArrays<HostPtr> A = sort_arrays(G, pass);
     const uint32_t base = tile * kSortTile + wave * (kSortTile / kSortWaves);
     uint32_t k[kSortItems], v[kSortItems], rank[kSortItems];
 #pragma unroll
@@ -256,7 +262,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(Batch b, uint32_t
             const uint32_t d = (k[it] >> shift) & mask;
             lpos[it] = tstart[d] + cnt[wave * nbins + d] + rank[it];
             if (lpos[it] < (uint32_t)kSortTile) stage[lpos[it]] = k[it];
-            else atomicOr(G.status, kStInternal);
+            else status_or(G, kStInternal);
         }
     }
     __syncthreads();
@@ -274,7 +280,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(Batch b, uint32_t
                 A.ok[g] = kk;
                 gpos[m] = g;
             } else {
-                atomicOr(G.status, kStInternal);
+                status_or(G, kStInternal);
             }
         }
     }
@@ -299,7 +305,7 @@ constexpr int kRangeItems = 4;
 __global__ __launch_bounds__(kElemThreads) void k_cell_ranges(Batch b)
 {
     const int gi = batch_grid(b);
-    const GridDev& G = *b.g[gi];
+    const GridView G = grid_view(b.g[gi]);
     const uint32_t tile = xcd_tile(b, gi);
 #pragma unroll
     for (int it = 0; it < kRangeItems; ++it) {

@@ -14,18 +14,22 @@ struct Trace {
     const char** names;  // cap entries, or null
     const char* only;    // kernel name to trace, or null for every kernel
     int cap, n;
+    hipError_t err;      // first failed event record
 };
 extern thread_local Trace* g_trace;
 
 bool trace_wants(const char* name);
 inline void trace_before(const char* name, hipStream_t s)
 {
-    if (trace_wants(name)) hipEventRecord(g_trace->ev[2 * g_trace->n], s);
+    if (!trace_wants(name)) return;
+    const hipError_t e = hipEventRecord(g_trace->ev[2 * g_trace->n], s);
+    if (g_trace->err == hipSuccess) g_trace->err = e;
 }
 inline void trace_after(const char* name, hipStream_t s)
 {
     if (!trace_wants(name)) return;
-    hipEventRecord(g_trace->ev[2 * g_trace->n + 1], s);
+    const hipError_t e = hipEventRecord(g_trace->ev[2 * g_trace->n + 1], s);
+    if (g_trace->err == hipSuccess) g_trace->err = e;
     if (g_trace->names) g_trace->names[g_trace->n] = name;
     g_trace->n++;
 }
