@@ -18,6 +18,11 @@ bracket the kernel nodes on this stack), and its algorithmic bytes per launch (t
 per-particle / per-cell figures below, times the units one launch processes) are divided by the
 mean launch duration.  HBM traffic comes from the committed counter summary of
 that kernel when its source has not changed since.
+
+Two execution modes follow the headline run (`modes` in the JSON line): a batch of 16 grids of
+mixed sizes stepped with one launch per kernel (against the same grids stepped one after
+another), and 64 streams served with Poisson arrivals through the serving runtime (request
+latency p50 / p99 at real time and at an accelerated replay).
 """
 from __future__ import annotations
 
@@ -203,6 +208,14 @@ def parse():
                          "until it is spent (0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one device copy of 1 GiB (for counter calibration)")
+    ap.add_argument("--batch-steps", type=int, default=20,
+                    help="timed cycles of the 16-grid batch (0: skip the batched mode)")
+    ap.add_argument("--serve-seconds", type=float, default=10.0,
+                    help="simulated seconds of the 64-stream serving replay (0: skip serving)")
+    ap.add_argument("--serve-speedups", default="1,10",
+                    help="replay speeds of the serving run (1 = real time)")
+    ap.add_argument("--serve-budget-gib", type=float, default=64.0,
+                    help="HBM budget for admitting serving streams")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="no GPU run: turn two rocprofv3 counter files into the traffic record")
     ap.add_argument("--traffic-command", action="append", default=[],
@@ -313,7 +326,7 @@ def main():
     cycle_ms = [gev[s][0].elapsed_time(gev[s][1]) for s in range(args.steps)]
     ms_per_step = wall * 1e3 / args.steps
     cycles_per_s = args.steps / wall
-    b_alg = B_PER_PARTICLE * nu + B_PER_BORN * nb + B_PER_CELL * C
+    bytes_cycle = b_alg(nu, nb, C)
 
     dom_ms = dom.durations_ms()
     dom_mean_ms = float(np.mean(dom_ms)) if dom_ms else float("nan")
@@ -358,10 +371,10 @@ def main():
                   "per_call_ms": per_call},
         "per_kernel_ms": per_kernel_ms,
         "launches_per_cycle": launches,
-        "cycle_roofline": {"bound": "hbm", "algorithmic_bytes": b_alg,
-                           "achieved": b_alg / (ms_per_step * 1e-3) / 1e9,
+        "cycle_roofline": {"bound": "hbm", "algorithmic_bytes": bytes_cycle,
+                           "achieved": bytes_cycle / (ms_per_step * 1e-3) / 1e9,
                            "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": b_alg / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS},
+                           "frac": bytes_cycle / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS},
         "roofline": {"kernel": dominant, "bound": "hbm", "achieved": dom_gbs,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": dom_gbs / HBM_PEAK_GBS,
                      "traffic": traffic, "algorithmic_bytes_per_launch": dom_bytes,
@@ -370,10 +383,171 @@ def main():
         "meas_generation_s": t_gen,
     }
 
+    modes = {}
+    if args.batch_steps > 0:
+        print("[bench] batched mode: 16 grids", file=sys.stderr, flush=True)
+        modes["batched_16_grids"] = bench_batched(args.batch_steps)
+    if args.serve_seconds > 0:
+        print("[bench] serving mode: 64 streams", file=sys.stderr, flush=True)
+        modes["served_64_streams"] = bench_served(
+            args.serve_seconds, [float(x) for x in args.serve_speedups.split(",") if x],
+            int(args.serve_budget_gib * (1 << 30)))
+    if modes:
+        out["modes"] = modes
+
     if args.cpu_seconds > 0:
         print(f"[bench] oracle on the host, {args.cpu_seconds:.0f} s", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(p, seq, args.cpu_seconds)
     print(json.dumps(out), flush=True)
+
+
+def b_alg(nu: int, nb: int, C: int) -> int:
+    return B_PER_PARTICLE * nu + B_PER_BORN * nb + B_PER_CELL * C
+
+
+def bench_batched(steps: int, warmup: int = 5):
+    """16 grids of mixed sizes (4x128^2, 4x256^2, 3x384^2, 3x512^2, 2x768^2, 8 particles and one
+    new-born slot per cell) stepped together, one launch per kernel for the whole batch, each
+    batched cycle captured as a HIP graph and replayed; then the same grids stepped one after
+    another (the plain per-grid loop, 16 x 12 launches per cycle), captured and replayed alike."""
+    import numpy as np
+    import torch
+
+    from paper_1605_02406_amd import dogm, scenes
+
+    dev = torch.device("cuda:0")
+    wls = [scenes.batch_workload(n, seed=i) for i, n in enumerate(scenes.BATCH_SIZES)]
+    n_cycles = warmup + 2 * steps
+    seqs = []
+    for wl in wls:
+        seqs.append([dogm.Meas(torch.as_tensor(m["m_occ"], device=dev),
+                               torch.as_tensor(m["m_free"], device=dev))
+                     for m in scenes.measurement_sequence(wl, n_cycles)])
+    grids = [dogm.Grid(dogm.make_params(wl["nx"], wl["ny"], wl["cell"], wl["n_pers"],
+                                        wl["n_born"], seed=i, grid_id=i, **scenes.FILTER))
+             for i, wl in enumerate(wls)]
+    for k in range(warmup):
+        dogm.step_batch(grids, [sq[k] for sq in seqs])
+    torch.cuda.synchronize()
+
+    def replay(graphs):
+        ev = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in graphs]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for e, gr in zip(ev, graphs):
+            e[0].record()
+            gr.replay()
+            e[1].record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        return wall, [e[0].elapsed_time(e[1]) for e in ev]
+
+    side = torch.cuda.Stream()
+    batched = []
+    for s in range(steps):
+        gr = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(gr, stream=side):
+            dogm.step_batch(grids, [sq[warmup + s] for sq in seqs])
+        batched.append(gr)
+    wall_b, ms_b = replay(batched)
+    looped = []
+    for s in range(steps):
+        gr = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(gr, stream=side):
+            for g, sq in zip(grids, seqs):
+                g.step(sq[warmup + steps + s])
+        looped.append(gr)
+    wall_l, ms_l = replay(looped)
+    status = [g.status() for g in grids]
+    nu = sum(wl["n_pers"] for wl in wls)
+    nb = sum(wl["n_born"] for wl in wls)
+    C = sum(wl["nx"] * wl["ny"] for wl in wls)
+    bytes_cycle = sum(b_alg(wl["n_pers"], wl["n_born"], wl["nx"] * wl["ny"]) for wl in wls)
+    ms = wall_b * 1e3 / steps
+    return {"grids": [f'{wl["nx"]}x{wl["ny"]}' for wl in wls], "cells": C, "n_pers": nu,
+            "n_born": nb, "steps": steps, "warmup": warmup,
+            "batched": {"ms_per_cycle": ms, "cycles_per_s": 1e3 / ms,
+                        "grid_cycles_per_s": len(wls) * 1e3 / ms,
+                        "particles_per_s": nu * 1e3 / ms,
+                        "cycle_ms_p50": float(np.percentile(ms_b, 50)),
+                        "cycle_ms_p99": float(np.percentile(ms_b, 99)),
+                        "roofline_frac": bytes_cycle / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
+            "per_grid_loop": {"ms_per_cycle": wall_l * 1e3 / steps,
+                              "cycles_per_s": steps / wall_l,
+                              "particles_per_s": nu * steps / wall_l},
+            "algorithmic_bytes_per_cycle": bytes_cycle, "status_words": status}
+
+
+def bench_served(seconds: float, speedups, budget: int, n_streams: int = 64, rate_hz: float = 10.0,
+                 pool: int = 4):
+    """64 streams of sizes drawn from {128^2, 256^2, 512^2} (8 particles and one new-born slot
+    per cell), each receiving measurement grids as a Poisson process of `rate_hz` over `seconds`
+    of simulated time, replayed at each speed in `speedups` through the serving runtime
+    (admission against `budget` bytes, continuous batching). Each stream cycles through `pool`
+    pre-uploaded measurement grids of its own scene."""
+    import numpy as np
+    import torch
+
+    from paper_1605_02406_amd import dogm, scenes
+    from paper_1605_02406_amd.serve import Server
+
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(1000)
+    sizes = rng.choice([128, 256, 512], size=n_streams)
+    wls = [scenes.batch_workload(int(n), seed=i) for i, n in enumerate(sizes)]
+    params = [dogm.make_params(wl["nx"], wl["ny"], wl["cell"], wl["n_pers"], wl["n_born"],
+                               seed=i, grid_id=i, **scenes.FILTER) for i, wl in enumerate(wls)]
+    meas = [[dogm.Meas(torch.as_tensor(m["m_occ"], device=dev),
+                       torch.as_tensor(m["m_free"], device=dev))
+             for m in scenes.measurement_sequence(wl, pool)] for wl in wls]
+    arrivals = []
+    for i in range(n_streams):
+        t = rng.exponential(1.0 / rate_hz)
+        while t < seconds:
+            arrivals.append((t, i))
+            t += rng.exponential(1.0 / rate_hz)
+    arrivals.sort()
+    runs = []
+    for speed in speedups:
+        srv = Server(budget)
+        admitted = [i for i in range(n_streams) if srv.open(i, params[i])]
+        # one untimed cycle of every admitted stream
+        for i in admitted:
+            srv.submit(i, meas[i][0])
+        srv.drain()
+        srv.stats.done.clear()
+        srv.stats.batches = srv.stats.batched_requests = 0
+        count = {i: 1 for i in admitted}
+        todo = [(t, i) for t, i in arrivals if i in count]
+        clock = srv.clock
+        t0 = clock()
+        nxt = 0
+        while nxt < len(todo) or srv.pending or srv.inflight:
+            now = clock()
+            while nxt < len(todo) and t0 + todo[nxt][0] / speed <= now:
+                t, i = todo[nxt]
+                srv.submit(i, meas[i][count[i] % pool], t_arrival=t0 + t / speed)
+                count[i] += 1
+                nxt += 1
+            srv.pump()
+        wall = clock() - t0
+        lat = np.array([r.latency for r in srv.stats.done]) * 1e3
+        runs.append({"speedup": speed, "requests": int(lat.size), "wall_s": wall,
+                     "requests_per_s": lat.size / wall,
+                     "latency_ms_p50": float(np.percentile(lat, 50)) if lat.size else None,
+                     "latency_ms_p99": float(np.percentile(lat, 99)) if lat.size else None,
+                     "latency_ms_max": float(lat.max()) if lat.size else None,
+                     "batches": srv.stats.batches,
+                     "mean_batch": srv.stats.batched_requests / max(srv.stats.batches, 1),
+                     "streams_admitted": len(admitted),
+                     "streams_rejected": srv.stats.rejected_streams,
+                     "hbm_reserved_bytes": srv.admission.used,
+                     "status_nonzero": sum(1 for i in admitted if srv.grids[i].status() != 0)})
+        del srv
+        torch.cuda.synchronize()
+    return {"streams": n_streams, "sizes": {str(n): int((sizes == n).sum()) for n in (128, 256, 512)},
+            "rate_hz_per_stream": rate_hz, "simulated_s": seconds, "budget_bytes": budget,
+            "runs": runs}
 
 
 def cpu_baseline(p, seq, budget_s):

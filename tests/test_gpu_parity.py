@@ -85,6 +85,13 @@ def test_large_scene_512_full_size():
     print("c512 stats:", stats[-1])
 
 
+def test_large_scene_1024_full_size():
+    """The 1024x1024 / 2^23 + 2^20 workload at full size (two sort passes of 11 and 10 bits),
+    per-call parity on full arrays in the second cycle."""
+    g, stats = run_scene("c1024", 2, check_from=2)
+    print("c1024 stats:", stats[-1])
+
+
 def _fresh(nx, ny, nu, nb, **kw):
     p = dogm.make_params(nx, ny, 0.2, nu, nb, **kw)
     return dogm.Grid(p), p
@@ -115,6 +122,22 @@ def test_vacuous_measurement_and_zero_weight():
     pc.cycle(device_meas(dict(m_occ=np.zeros(C), m_free=np.zeros(C))))
     assert int(g.v["S_fixed"].item()) == 0 and int(g.v["W_fixed"].item()) == 0
     assert np.all(u32(g.v["bkey"]) == C)
+
+
+@pytest.mark.parametrize("nx,ny,nu,nb", [
+    (40, 40, 20000, 3000),      # keys < 2^11: one pass of 11 bits
+    (1500, 1500, 60000, 5000),  # keys < 2^22: two passes of 11 bits
+    (2048, 2048, 60000, 5000),  # keys < 2^23: three passes of 8, 8 and 7 bits
+])
+def test_sort_plans(nx, ny, nu, nb):
+    """Grids whose key range needs one, two and three radix passes with the widest digits,
+    from arbitrary particle states, two cycles of per-call parity."""
+    g, p = _fresh(nx, ny, nu, nb, seed=7, grid_id=3)
+    g.load_state(scenes.random_particles(p.nx, p.ny, p.cell_size, p.n_pers, 7))
+    pc = PerCall(g)
+    for k in range(2):
+        print(f"[parity] sort plan {nx}x{ny} cycle {k + 1}", flush=True)
+        pc.cycle(device_meas(scenes.random_measurement(p.nx * p.ny, 20 + k)))
 
 
 def test_random_states_and_measurements():
@@ -168,6 +191,30 @@ def test_batch_equals_single_grids():
         assert g.cycle == 4
         for k, v in g.v.items():
             assert np.array_equal(host(v), ref[k]), k
+
+
+def test_batch_of_16_mixed_grids_at_full_size():
+    """The 16-grid mix the benchmark's batched mode runs (128^2 to 768^2, 8 particles and one
+    new-born slot per cell), two cycles in one batch, equals each grid stepped alone."""
+    wls = [scenes.batch_workload(n, seed=i) for i, n in enumerate(scenes.BATCH_SIZES)]
+    seqs = [[device_meas(m) for m in scenes.measurement_sequence(wl, 2)] for wl in wls]
+    single = []
+    for i, (wl, seq) in enumerate(zip(wls, seqs)):
+        g = dogm.Grid(wl_params(wl, seed=i, grid_id=i))
+        for m in seq:
+            g.step(m)
+        torch.cuda.synchronize()
+        single.append({k: host(v).copy() for k, v in g.v.items()})
+        del g
+    grids = [dogm.Grid(wl_params(wl, seed=i, grid_id=i)) for i, wl in enumerate(wls)]
+    for k in range(2):
+        print(f"[parity] 16-grid batch cycle {k + 1}", flush=True)
+        dogm.step_batch(grids, [seq[k] for seq in seqs])
+    torch.cuda.synchronize()
+    for i, (g, ref) in enumerate(zip(grids, single)):
+        assert g.status() == 0
+        for k, v in g.v.items():
+            assert np.array_equal(host(v), ref[k]), (i, k)
 
 
 def test_graph_replays_equal_eager_steps():
