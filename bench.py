@@ -49,7 +49,7 @@ B_PER_CELL = 92
 CSRC = os.path.join(ROOT, "paper_1605_02406_amd", "csrc")
 KERNEL_SOURCE = {
     "k_predict": "k_particles.hip", "k_sort_hist": "k_sort.hip", "k_scan_rows": "k_sort.hip",
-    "k_sort_scatter": "k_sort.hip", "k_cell_ranges": "k_sort.hip", "k_seg_sums<false>": "k_cells.hip",
+    "k_sort_scatter": "k_sort.hip", "k_seg_sums<false>": "k_cells.hip",
     "k_seg_sums<true>": "k_cells.hip", "k_cells<false>": "k_cells.hip",
     "k_cells<true>": "k_cells.hip", "k_seg_moments": "k_cells.hip",
     "k_born_offsets": "k_particles.hip", "k_particle_tiles": "k_particles.hip",
@@ -74,10 +74,10 @@ def algorithmic_bytes(kernel: str, nu: int, nb: int, C: int) -> float:
     cycle where they differ), from per-unit figures: predict reads x, y, vx, vy, w (20 B) and
     writes them and the key (24 B); a sort pass reads the key, the source index (from the
     second pass on) and the five state arrays and writes key, index and state (28 B); the
-    cell ranges read the sorted keys (4 B) and write two words per cell (8 B); the
     resampling reads every joint weight (4 B), the state of each chosen source (16 B) and
-    writes the 20-byte state of every output; the per-cell sums read the sorted key, weight
-    and velocity (16 B per particle) and write ranges and six FP64 sums per cell (56 B); the
+    writes the 20-byte state of every output; the per-cell pass of the assignment reads the
+    sorted key, weight and velocity (16 B per particle) and writes the cell range and six FP64
+    sums per cell (64 B); the
     cell pass reads ranges, sums, m_F and the measurement (68 B) and writes masses,
     normalisers and moments (61 B) per cell."""
     bits = sort_plan(C)
@@ -86,15 +86,15 @@ def algorithmic_bytes(kernel: str, nu: int, nb: int, C: int) -> float:
     if kernel == "k_sort_scatter":
         per = [(24 if q == 0 else 28) + 28 for q in range(len(bits))]
         return nu * sum(per) / len(per)
-    if kernel == "k_cell_ranges":
-        return 4.0 * nu + 8.0 * C
     if kernel == "k_sort_hist":
         return 4.0 * nu
     if kernel == "k_scan_rows":
         tiles = -(-nu // 1024)
         return 8.0 * sum(1 << b for b in bits) * tiles / len(bits)
-    if kernel in ("k_seg_sums<false>", "k_seg_sums<true>"):
-        return 16.0 * nu + 56.0 * C
+    if kernel == "k_seg_sums<false>":
+        return 16.0 * nu + 64.0 * C
+    if kernel == "k_seg_sums<true>":
+        return 16.0 * nu + 16.0 * C
     if kernel in ("k_cells<false>", "k_cells<true>"):
         return (68.0 + 61.0) * C
     if kernel == "k_resample":

@@ -159,7 +159,9 @@ int dogm_view(const dogm_grid* grid, dogm_views* views);
 int dogm_predict(dogm_grid* grid);
 
 /* Alg. 2: stable sort of the particles by cell key into sx..sw / skey / perm, and the
- * particle range of every cell (cell_start, cell_end; empty cells have start == end). */
+ * particle range of every cell (cell_start, cell_end; empty cells have start == end).  The same
+ * pass over the sorted particles also forms the per-cell sums the update reads (sum of weights
+ * and, for Alg. 6, of the weighted velocities), which do not depend on the measurement. */
 int dogm_assign(dogm_grid* grid);
 
 /* Alg. 3, 4 and 5 in the paper's order:

@@ -47,6 +47,7 @@ constexpr int kCellThreads = 256;
 constexpr int kSegThreads = 256;
 constexpr int kSegItems = 8;
 constexpr int kSegRange = kWave * kSegItems;                           // 512
+static_assert(kSegItems % 4 == 0, "a lane reads its items as 16-byte vectors");
 constexpr int kSegBlockParticles = (kSegThreads / kWave) * kSegRange;  // 2048
 
 // New-born slots are initialised in tiles of kBornTile slots (one per thread); their fixed-point
@@ -77,6 +78,9 @@ using ConstPtr = __attribute__((address_space(4))) const T*;  // read-only while
 // the byte offset in 32 bits (every array holds fewer than 2^30 elements of at most 8 bytes),
 // so the compiler addresses it with a scalar base and one 32-bit offset register instead of a
 // 64-bit address pair per access.  Same size and bits as a plain pointer.
+using u32x4 = uint32_t __attribute__((ext_vector_type(4)));
+using f32x4 = float __attribute__((ext_vector_type(4)));
+
 template <typename T>
 struct GArr {
     GlobalPtr<T> p;
@@ -87,6 +91,14 @@ struct GArr {
     }
     __device__ __forceinline__ __attribute__((address_space(1))) T& operator*() const { return *p; }
     __device__ __forceinline__ explicit operator bool() const { return p != nullptr; }
+    // V = a vector of sizeof(V) / sizeof(T) elements from element i (aligned to sizeof(V))
+    template <typename V>
+    __device__ __forceinline__ V load_vec(uint32_t i) const
+    {
+        using Byte = __attribute__((address_space(1))) unsigned char;
+        return *(__attribute__((address_space(1))) const V*)((Byte*)(GlobalPtr<void>)p +
+                                                             i * (uint32_t)sizeof(T));
+    }
 };
 
 template <template <typename> class P>

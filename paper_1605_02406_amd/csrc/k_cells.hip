@@ -1,6 +1,6 @@
-// Per-cell work over the sorted particles and the cell ranges that the sort recorded (Alg. 2):
-// the Dempster-Shafer cell update with the new-born split (Alg. 3), the normalisation components
-// of the persistent update (Alg. 4) and the velocity moments (Alg. 6).
+// Per-cell work over the sorted particles: the particle range of every cell (Alg. 2), the
+// Dempster-Shafer cell update with the new-born split (Alg. 3), the normalisation components of
+// the persistent update (Alg. 4) and the velocity moments (Alg. 6).
 //
 // Two passes.  The first is particle-parallel: per-cell sums are segmented reductions over the
 // sorted particles instead of the paper's prefix-sum differences (a global FP32 prefix loses the
@@ -10,7 +10,8 @@
 // segmented scan across the lanes joins the cells that span lanes; the running sum of a cell
 // still open at the end of the chunk is carried into the next one.  Accumulators are FP64 and
 // the summation order depends only on the data, never on the launch or the batch.  A closed
-// cell only stores its sums.  The second pass is cell-parallel: one thread per cell
+// cell only stores its sums; the particles where a cell's run opens and closes store its range.
+// The second pass is cell-parallel: one thread per cell
 // (empty or not) runs the update with every lane of the wave busy.
 //
 // Without velocity evidence (p_A = 0) the updated persistent weights are w' = mu_UA w, so the
@@ -27,9 +28,10 @@ constexpr uint32_t kNone = 0xFFFFFFFFu;
 // One wave's share of a segmented reduction with NV FP64 sums per particle.
 //   val(k, w, vx, vy, v): v[0..NV) of a particle of cell k with weight w and velocity (vx, vy)
 //   emit(k, v)          : the complete sums of cell k (called once per cell, by one lane)
-// The cell ranges recorded by the sort decide where the wave starts (after the cell that began
-// before its share) and ends (with the cell that holds its last particle).
-template <int NV, typename Val, typename Emit>
+// The wave finds its first cell from the keys (the first particle whose cell differs from the
+// one before the wave's share) and finishes the cell of its last particle past its share.
+// kRanges: also store the range of every cell it handles.
+template <int NV, bool kRanges, typename Val, typename Emit>
 __device__ __forceinline__ void seg_reduce(const GridView& G, uint32_t wave_index, Val val,
                                            Emit emit)
 {
@@ -45,36 +47,70 @@ __device__ __forceinline__ void seg_reduce(const GridView& G, uint32_t wave_inde
     float pw[kSegItems], pvx[kSegItems], pvy[kSegItems];
     auto load_chunk = [&](uint32_t base, uint32_t bound) {
         const uint32_t i0 = base + lane * kSegItems;
+        if (i0 + kSegItems <= bound) {  // a lane's items are whole 16-byte vectors
 #pragma unroll
-        for (int it = 0; it < kSegItems; ++it) {
-            const uint32_t i = i0 + it;
-            key[it] = (i < bound) ? G.skey[i] : kNone;
-            pw[it] = (i < bound) ? G.sw[i] : 0.0f;
-            pvx[it] = (i < bound) ? G.svx[i] : 0.0f;
-            pvy[it] = (i < bound) ? G.svy[i] : 0.0f;
+            for (int q = 0; q < kSegItems; q += 4) {
+                const u32x4 k4 = G.skey.load_vec<u32x4>(i0 + q);
+                const f32x4 w4 = G.sw.load_vec<f32x4>(i0 + q);
+                const f32x4 x4 = G.svx.load_vec<f32x4>(i0 + q);
+                const f32x4 y4 = G.svy.load_vec<f32x4>(i0 + q);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    key[q + e] = k4[e];
+                    pw[q + e] = w4[e];
+                    pvx[q + e] = x4[e];
+                    pvy[q + e] = y4[e];
+                }
+            }
+        } else {
+#pragma unroll
+            for (int it = 0; it < kSegItems; ++it) {
+                const uint32_t i = i0 + it;
+                key[it] = (i < bound) ? G.skey[i] : kNone;
+                pw[it] = (i < bound) ? G.sw[i] : 0.0f;
+                pvx[it] = (i < bound) ? G.svx[i] : 0.0f;
+                pvy[it] = (i < bound) ? G.svy[i] : 0.0f;
+            }
         }
     };
     load_chunk(a, b);
-    const uint32_t ka = G.skey[a];
     const uint32_t kprev = a > 0 ? G.skey[a - 1] : kNone;
-    const uint32_t kl = G.skey[b - 1];
-    if (ka >= C) return;  // only particles outside the grid from here on
-    const uint32_t p0 = (kprev == ka) ? G.cend[ka] : a;
-    if (p0 >= b) return;
-    const uint32_t pend = kl < C ? G.cend[kl] : b;
+    // p0: the first particle in [a, b) whose cell differs from that of the particle before a
+    // (keys past b read as kNone, so a wave whose range holds no cell start finds p0 >= b)
+    uint32_t lfirst = kSegItems, kfirst = kNone;
+#pragma unroll
+    for (int it = kSegItems - 1; it >= 0; --it)
+        if (key[it] != kprev) {
+            lfirst = it;
+            kfirst = key[it];
+        }
+    const uint64_t has = __ballot(lfirst < (uint32_t)kSegItems);
+    if (has == 0) return;
+    const int l0 = __ffsll((unsigned long long)has) - 1;
+    const uint32_t p0 = a + l0 * kSegItems + __shfl(lfirst, l0, kWave);
+    if (p0 >= b || __shfl(kfirst, l0, kWave) >= C) return;  // no cell starts here
+    // the cell of the range's last particle, which this wave finishes past b
+    const uint32_t ib = (b - 1 - a) % kSegItems;
+    uint32_t kb = kNone;
+#pragma unroll
+    for (int it = 0; it < kSegItems; ++it)
+        if ((uint32_t)it == ib) kb = key[it];
+    const uint32_t kl = __shfl(kb, (int)((b - 1 - a) / kSegItems), kWave);
 
     double carry[NV];
 #pragma unroll
     for (int j = 0; j < NV; ++j) carry[j] = 0.0;
     uint32_t carry_key = kNone;
+    uint32_t before_chunk = kNone;  // masked key of the particle before the chunk
 
-    for (uint32_t base = a; base < pend; base += kSegRange) {
-        if (base != a) load_chunk(base, pend);
+    for (uint32_t base = a;; base += kSegRange) {
+        if (base != a) load_chunk(base, n);
         const uint32_t i0 = base + lane * kSegItems;
+        // particles outside [p0, end of kl's run) and outside the grid take no part
 #pragma unroll
         for (int it = 0; it < kSegItems; ++it) {
             const uint32_t i = i0 + it;
-            if (i < p0 || i >= pend || key[it] >= C) key[it] = kNone;
+            if (i < p0 || key[it] >= C || (i >= b && key[it] != kl)) key[it] = kNone;
         }
         const uint32_t first = key[0];
         uint32_t cur = key[0];
@@ -145,14 +181,31 @@ __device__ __forceinline__ void seg_reduce(const GridView& G, uint32_t wave_inde
         // a tail cell ends here unless the next lane (or the next chunk) continues it
         uint32_t next_first = __shfl_down(first, 1, kWave);
         if (lane == kWave - 1) {
-            const uint32_t inext = base + kSegRange;
-            next_first = (inext < pend) ? G.skey[inext] : kNone;
-            if (next_first >= C) next_first = kNone;
+            const uint32_t inext = base + kSegRange;  // >= b: only kl's run continues
+            next_first = (inext < n) ? G.skey[inext] : kNone;
+            if (next_first >= C || next_first != kl) next_first = kNone;
         }
         if (cur != kNone && next_first != cur) emit(cur, run);
+        if (kRanges) {
+            // Alg. 2: a particle whose neighbour before (after) it belongs to another cell
+            // opens (closes) its cell's run
+            const uint32_t up = __shfl_up(key[kSegItems - 1], 1, kWave);  // every lane takes part
+            const uint32_t left = lane == 0 ? before_chunk : up;
+#pragma unroll
+            for (int it = 0; it < kSegItems; ++it) {
+                const uint32_t k = key[it];
+                if (k == kNone) continue;
+                const uint32_t kp = it == 0 ? left : key[it - 1];
+                const uint32_t kn = it == kSegItems - 1 ? next_first : key[it + 1];
+                if (kp != k) G.cstart[k] = i0 + it;
+                if (kn != k) G.cend[k] = i0 + it + 1;
+            }
+        }
+        before_chunk = __shfl(key[kSegItems - 1], kWave - 1, kWave);
         const uint32_t t63 = __shfl(cur, kWave - 1, kWave);
         const uint32_t n63 = __shfl(next_first, kWave - 1, kWave);
         carry_key = (t63 != kNone && n63 == t63) ? t63 : kNone;
+        if (carry_key == kNone) break;
 #pragma unroll
         for (int j = 0; j < NV; ++j) carry[j] = __shfl(run[j], kWave - 1, kWave);
     }
@@ -235,8 +288,10 @@ __device__ __forceinline__ void write_moments(const GridView& G, uint32_t c, boo
 }
 
 // ----------------------------------------------------------------------------------------------
-// Pass 1: per-cell sums of the cells that hold particles (Alg. 3 sum, Alg. 4 sum of g w, Alg. 6
-// sums without velocity evidence).
+// Pass 1: per-cell sums of the cells that hold particles.  Without evidence (launched by the
+// assignment, since nothing in it depends on the measurement): the particle range of every
+// occupied cell (Alg. 2), the sum of weights (Alg. 3) and the weighted velocity sums (Alg. 6).
+// With evidence (launched by the update): the sums of w and of g w (Alg. 3, Alg. 4).
 // ----------------------------------------------------------------------------------------------
 
 template <bool kAssoc>
@@ -248,7 +303,7 @@ __global__ __launch_bounds__(kSegThreads) void k_seg_sums(Batch b)
     const uint32_t tile = xcd_tile(b, gi);
     const uint32_t wave = tile * (kSegThreads / kWave) + threadIdx.x / kWave;
     if (kAssoc) {
-        seg_reduce<2>(
+        seg_reduce<2, false>(
             G, wave,
             [&](uint32_t k, float w, float vx, float vy, double* v) {
                 v[0] = (double)w;
@@ -260,7 +315,7 @@ __global__ __launch_bounds__(kSegThreads) void k_seg_sums(Batch b)
                 G.sum_wt[k] = v[1];
             });
     } else {
-        seg_reduce<6>(
+        seg_reduce<6, true>(
             G, wave,
             [&](uint32_t, float w, float vx, float vy, double* v) {
                 const double wd = (double)w, x = (double)vx, y = (double)vy;
@@ -321,6 +376,16 @@ __global__ __launch_bounds__(kCellThreads) void k_cells(Batch b)
     if (threadIdx.x == 0) G.bpart[part] = qsum;
 }
 
+hipError_t launch_cell_sums(const GridRef* g, int n, hipStream_t s)
+{
+    Batch b;
+    const uint32_t blocks = make_batch(b, g, n, [](const GridDev& G) {
+        return xcd_blocks(ceil_div(G.nu, kSegBlockParticles));
+    });
+    if (blocks) DOGM_LAUNCH(k_seg_sums<false>, dim3(blocks), dim3(kSegThreads), 0, s, b);
+    return hipGetLastError();
+}
+
 hipError_t launch_update(const GridRef* g, int n, hipStream_t s)
 {
     bool any_assoc = false, all_assoc = true;
@@ -330,14 +395,12 @@ hipError_t launch_update(const GridRef* g, int n, hipStream_t s)
     }
     if (any_assoc && !all_assoc) return hipErrorInvalidValue;  // one kind per launch
     Batch b;
-    uint32_t blocks = make_batch(b, g, n, [](const GridDev& G) {
-        return xcd_blocks(ceil_div(G.nu, kSegBlockParticles));
-    });
-    if (blocks) {
-        if (any_assoc)
-            DOGM_LAUNCH(k_seg_sums<true>, dim3(blocks), dim3(kSegThreads), 0, s, b);
-        else
-            DOGM_LAUNCH(k_seg_sums<false>, dim3(blocks), dim3(kSegThreads), 0, s, b);
+    uint32_t blocks = 0;
+    if (any_assoc) {  // without evidence the assignment already formed the sums
+        blocks = make_batch(b, g, n, [](const GridDev& G) {
+            return xcd_blocks(ceil_div(G.nu, kSegBlockParticles));
+        });
+        if (blocks) DOGM_LAUNCH(k_seg_sums<true>, dim3(blocks), dim3(kSegThreads), 0, s, b);
     }
     blocks = make_batch(b, g, n, [](const GridDev& G) { return G.n_cell_parts; });
     if (blocks) {
@@ -362,7 +425,7 @@ __global__ __launch_bounds__(kSegThreads) void k_seg_moments(Batch b)
     const GridView G = grid_view(b.g[gi]);
     const uint32_t tile = xcd_tile(b, gi);
     const uint32_t wave = tile * (kSegThreads / kWave) + threadIdx.x / kWave;
-    seg_reduce<5>(
+    seg_reduce<5, false>(
         G, wave,
         [&](uint32_t, float w, float vx, float vy, double* v) {
             const double wd = (double)w, x = (double)vx, y = (double)vy;

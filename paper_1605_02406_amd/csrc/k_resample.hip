@@ -17,6 +17,7 @@ namespace dogm {
 
 constexpr int kResWaves = kResThreads / kWave;
 constexpr int kResRounds = kResItems;  // each wave owns kResRounds * 64 consecutive items
+static_assert(kResRounds % 4 == 0, "a lane reads its weights as 16-byte vectors");
 
 __device__ __forceinline__ uint64_t draw_floor(uint32_t j, double U, double spacing)
 {
@@ -67,10 +68,19 @@ __global__ __launch_bounds__(kResThreads) void k_resample(Batch b)
     const uint32_t lbase = wbase + lane * kResRounds;
     const auto wsrc = born ? G.bw : G.sw;
     float wl[kResRounds];
+    if (lbase + kResRounds <= n_src) {  // whole 16-byte vectors
 #pragma unroll
-    for (int r = 0; r < kResRounds; ++r) {
-        const uint32_t i = lbase + r;
-        wl[r] = i < n_src ? wsrc[i] : 0.0f;
+        for (int r = 0; r < kResRounds; r += 4) {
+            const f32x4 v = wsrc.load_vec<f32x4>(lbase + r);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) wl[r + e] = v[e];
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < kResRounds; ++r) {
+            const uint32_t i = lbase + r;
+            wl[r] = i < n_src ? wsrc[i] : 0.0f;
+        }
     }
 
     // joint weight before this tile and in total, from the partial sums of the persistent tiles

@@ -4,8 +4,8 @@
 // each pass moves the key, the source index and the FP32 particle state.  A pass is three
 // kernels that communicate only through memory: the digit histogram of every tile (for the
 // first pass it comes from the prediction kernel), a scan of each digit's row of tile counts,
-// and the scatter.  No block waits for another.  A last kernel marks where each cell's run of
-// sorted particles starts and ends.
+// and the scatter.  No block waits for another.  The per-cell pass that follows the sort marks
+// where each cell's run of sorted particles starts and ends.
 //
 // Stable ranking inside a tile: each of the block's 16 waves owns a contiguous sixteenth of the
 // tile (256 keys) and walks it 64 keys at a time; lanes holding the same digit find each other
@@ -164,6 +164,22 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(Batch b, uint32_t
     if (tile >= G.n_sort_tiles) return;
     const uint32_t shift = G.dshift[pass], bits = G.dbits[pass];
     const uint32_t nbins = 1u << bits, mask = nbins - 1u;
+    // each thread owns a contiguous run of digits; their totals over all tiles and their counts
+    // in the tiles before this one do not depend on the tile's keys and are read first
+    constexpr int kMaxDpt = kSortBins / kSortThreads;
+    const uint32_t dpt = nbins >= (uint32_t)kSortThreads ? nbins / kSortThreads : 1u;
+    const uint32_t d0 = threadIdx.x * dpt;
+    const bool owner = d0 < nbins;
+    uint32_t gl[kMaxDpt], before[kMaxDpt];
+    if (owner) {
+#pragma unroll
+        for (int j = 0; j < kMaxDpt; ++j) {
+            if ((uint32_t)j >= dpt) break;
+            const uint32_t d = d0 + j;
+            gl[j] = G.rowtot[d];
+            before[j] = G.hist[d * G.n_hist_tiles + tile * (kSortTile / kHistTile)];
+        }
+    }
     const int wave = threadIdx.x / kWave;
     const int lane = lane_id();
     const uint64_t lt_mask = (1ull << lane) - 1ull;
@@ -211,14 +227,9 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(Batch b, uint32_t
     }
     __syncthreads();
 
-    // each thread owns a contiguous run of digits: wave offsets inside the digit, the tile's
-    // digit totals (local starts) and the digit's global start (all earlier digits, then this
-    // digit in all earlier tiles)
-    constexpr int kMaxDpt = kSortBins / kSortThreads;
-    const uint32_t dpt = nbins >= (uint32_t)kSortThreads ? nbins / kSortThreads : 1u;
-    const uint32_t d0 = threadIdx.x * dpt;
-    const bool owner = d0 < nbins;
-    uint32_t tot[kMaxDpt], gl[kMaxDpt];
+    // per owned digit: wave offsets inside the digit, the tile's digit totals (local starts)
+    // and the digit's global start (all earlier digits, then this digit in all earlier tiles)
+    uint32_t tot[kMaxDpt];
     uint32_t my_tot = 0, my_gl = 0;
     if (owner) {
 #pragma unroll
@@ -233,7 +244,6 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(Batch b, uint32_t
             }
             tot[j] = acc;
             my_tot += acc;
-            gl[j] = G.rowtot[d];
             my_gl += gl[j];
         }
     }
@@ -246,7 +256,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(Batch b, uint32_t
             if ((uint32_t)j >= dpt) break;
             const uint32_t d = d0 + j;
             tstart[d] = lrun;
-            goff[d] = grun + G.hist[d * G.n_hist_tiles + tile * (kSortTile / kHistTile)];
+            goff[d] = grun + before[j];
             lrun += tot[j];
             grun += gl[j];
         }
@@ -298,26 +308,6 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(Batch b, uint32_t
     move_out(pa, A.ow, stage, lpos, gpos);
 }
 
-// The particle range of every cell: its first and one-past-last sorted position (the
-// prediction cleared them, so empty cells keep start == end).
-constexpr int kRangeItems = 4;
-
-__global__ __launch_bounds__(kElemThreads) void k_cell_ranges(Batch b)
-{
-    const int gi = batch_grid(b);
-    const GridView G = grid_view(b.g[gi]);
-    const uint32_t tile = xcd_tile(b, gi);
-#pragma unroll
-    for (int it = 0; it < kRangeItems; ++it) {
-        const uint32_t i = (tile * kRangeItems + it) * kElemThreads + threadIdx.x;
-        if (i >= G.nu) continue;
-        const uint32_t k = G.skey[i];
-        if (k >= G.C) continue;
-        if (i == 0 || G.skey[i - 1] != k) G.cstart[k] = i;
-        if (i + 1 == G.nu || G.skey[i + 1] != k) G.cend[k] = i + 1;
-    }
-}
-
 hipError_t launch_sort(const GridRef* g, int n, hipStream_t s)
 {
     static bool lds_limit_set = false;
@@ -357,12 +347,9 @@ hipError_t launch_sort(const GridRef* g, int n, hipStream_t s)
                            sizeof(uint32_t) * (2 * (size_t)nbins + kSortTile);
         if (tiles) DOGM_LAUNCH(k_sort_scatter, dim3(tiles), dim3(kSortThreads), lds, s, b, pass);
     }
-    Batch b;
-    const uint32_t blocks = make_batch(b, g, n, [](const GridDev& G) {
-        return xcd_blocks(ceil_div(G.nu, kRangeItems * kElemThreads));
-    });
-    if (blocks) DOGM_LAUNCH(k_cell_ranges, dim3(blocks), dim3(kElemThreads), 0, s, b);
-    return hipGetLastError();
+    // the particle range of every occupied cell, with the per-cell sums of the update
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? launch_cell_sums(g, n, s) : e;
 }
 
 }  // namespace dogm

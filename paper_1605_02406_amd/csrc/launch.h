@@ -82,6 +82,7 @@ hipError_t launch_init(const GridRef* g, int n, hipStream_t s);
 hipError_t launch_set_cycle(const GridRef* g, int n, uint32_t cycle, hipStream_t s);
 hipError_t launch_predict(const GridRef* g, int n, hipStream_t s);        // Alg. 1
 hipError_t launch_sort(const GridRef* g, int n, hipStream_t s);           // Alg. 2 (sort)
+hipError_t launch_cell_sums(const GridRef* g, int n, hipStream_t s);      // Alg. 2 ranges + sums
 hipError_t launch_update(const GridRef* g, int n, hipStream_t s);         // Alg. 3, 4, 5
 hipError_t launch_born_offsets(const GridRef* g, int n, hipStream_t s);   // Alg. 5 (slots)
 hipError_t launch_particle_tiles(const GridRef* g, int n, hipStream_t s); // Alg. 4 + 5
