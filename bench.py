@@ -77,9 +77,10 @@ def algorithmic_bytes(kernel: str, nu: int, nb: int, C: int) -> float:
     resampling reads every joint weight (4 B), the state of each chosen source (16 B) and
     writes the 20-byte state of every output; the per-cell pass of the assignment reads the
     sorted key, weight and velocity (16 B per particle) and writes the cell range and six FP64
-    sums per cell (64 B); the
-    cell pass reads ranges, sums, m_F and the measurement (68 B) and writes masses,
-    normalisers and moments (61 B) per cell."""
+    sums per cell (64 B); the cell pass reads ranges, sums, m_F and the measurement (68 B) and
+    writes masses, normalisers and moments (61 B) per cell; the slot offsets read rho_b and
+    write o_c (8 B per cell); the tile pass rescales the persistent weights (key and weight
+    read, weight written: 12 B per particle) and writes each new-born slot's 25-byte record."""
     bits = sort_plan(C)
     if kernel == "k_predict":
         return 44.0 * nu
@@ -115,14 +116,17 @@ def source_digest(kernel: str) -> str:
     return h.hexdigest()
 
 
-def traffic_path(workload: str) -> str:
-    return os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+PROFILES = os.path.join(ROOT, "profiles")
 
 
-def measured_traffic(kernel: str, workload: str):
+def traffic_path(workload: str, outdir: str = PROFILES) -> str:
+    return os.path.join(outdir, f"traffic_{workload}.json")
+
+
+def measured_traffic(kernel: str, workload: str, outdir: str = PROFILES):
     """HBM bytes per launch from the committed counter summary, or None if there is none or
     the kernel's source changed since the counters were taken."""
-    path = traffic_path(workload)
+    path = traffic_path(workload, outdir)
     if not os.path.exists(path):
         return None
     with open(path) as fh:
@@ -138,7 +142,7 @@ def short_name(full: str) -> str:
     return name
 
 
-def write_traffic(fetch_csv: str, write_csv: str, workload: str, commands):
+def write_traffic(fetch_csv: str, write_csv: str, workload: str, commands, outdir: str = PROFILES):
     """Turns two rocprofv3 counter passes (FETCH_SIZE, WRITE_SIZE; KiB per dispatch) into HBM
     bytes per launch of every kernel, calibrated by the same counters on the 1 GiB device copy
     that --copy-calibration runs, and writes the JSON record and a markdown table."""
@@ -190,10 +194,10 @@ def write_traffic(fetch_csv: str, write_csv: str, workload: str, commands):
                                 "source_sha256": source_digest(name)}
         lines.append(f"| `{name}` | {len(f[full])} | {fk:.0f} | {wk:.0f} | {rd / 1e6:.1f} | "
                      f"{wr / 1e6:.1f} | {alg / 1e6:.1f} | {(rd + wr) / alg:.2f} |")
-    with open(traffic_path(workload), "w") as fh:
+    with open(traffic_path(workload, outdir), "w") as fh:
         json.dump(rec, fh, indent=1)
         fh.write("\n")
-    with open(os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}.md"), "w") as fh:
+    with open(os.path.join(outdir, f"hbm_traffic_{workload}.md"), "w") as fh:
         fh.write("\n".join(lines) + "\n")
 
 

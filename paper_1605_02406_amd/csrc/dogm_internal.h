@@ -54,11 +54,16 @@ constexpr int kSegBlockParticles = (kSegThreads / kWave) * kSegRange;  // 2048
 // weight sums follow the persistent tiles' sums in the resampling's list of partial sums.
 constexpr int kBornTile = 256;
 
-// Resampling: tiles of persistent particles, then tiles of new-born slots.
+// Resampling: tiles of persistent particles, then tiles of new-born slots; the joint weight of
+// each tile is a fixed-point partial sum formed by the persistent weight update.
 constexpr int kResThreads = 256;
-constexpr int kResItems = 8;
-constexpr int kResTile = kResThreads * kResItems;  // 2048
+constexpr int kResItems = 4;
+constexpr int kResTile = kResThreads * kResItems;  // 1024
 static_assert(kResTile % kBornTile == 0, "a resampling tile covers whole new-born tiles");
+// The persistent weight update walks kPtSplit resampling tiles per block.
+constexpr int kPtSplit = 2;
+constexpr int kPtItems = kResItems * kPtSplit;
+constexpr int kPtTile = kResTile * kPtSplit;  // 2048
 
 constexpr int kElemThreads = 256;  // element-wise kernels
 

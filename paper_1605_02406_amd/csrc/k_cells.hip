@@ -42,21 +42,34 @@ __device__ __forceinline__ void seg_reduce(const GridView& G, uint32_t wave_inde
     const uint32_t b = min(a + (uint32_t)kSegRange, n);
 
     // chunks of kSegRange particles at fixed offsets from a; the first chunk is read while the
-    // wave's range is looked up (particles before p0 or past pend are masked out below)
+    // wave's first cell is looked up (particles before p0 are masked out below)
     uint32_t key[kSegItems];
     float pw[kSegItems], pvx[kSegItems], pvy[kSegItems];
-    auto load_chunk = [&](uint32_t base, uint32_t bound) {
+    auto load_keys = [&](uint32_t base, uint32_t bound) {
         const uint32_t i0 = base + lane * kSegItems;
         if (i0 + kSegItems <= bound) {  // a lane's items are whole 16-byte vectors
 #pragma unroll
             for (int q = 0; q < kSegItems; q += 4) {
                 const u32x4 k4 = G.skey.load_vec<u32x4>(i0 + q);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) key[q + e] = k4[e];
+            }
+        } else {
+#pragma unroll
+            for (int it = 0; it < kSegItems; ++it)
+                key[it] = (i0 + it < bound) ? G.skey[i0 + it] : kNone;
+        }
+    };
+    auto load_state = [&](uint32_t base, uint32_t bound) {
+        const uint32_t i0 = base + lane * kSegItems;
+        if (i0 + kSegItems <= bound) {
+#pragma unroll
+            for (int q = 0; q < kSegItems; q += 4) {
                 const f32x4 w4 = G.sw.load_vec<f32x4>(i0 + q);
                 const f32x4 x4 = G.svx.load_vec<f32x4>(i0 + q);
                 const f32x4 y4 = G.svy.load_vec<f32x4>(i0 + q);
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
-                    key[q + e] = k4[e];
                     pw[q + e] = w4[e];
                     pvx[q + e] = x4[e];
                     pvy[q + e] = y4[e];
@@ -66,14 +79,14 @@ __device__ __forceinline__ void seg_reduce(const GridView& G, uint32_t wave_inde
 #pragma unroll
             for (int it = 0; it < kSegItems; ++it) {
                 const uint32_t i = i0 + it;
-                key[it] = (i < bound) ? G.skey[i] : kNone;
                 pw[it] = (i < bound) ? G.sw[i] : 0.0f;
                 pvx[it] = (i < bound) ? G.svx[i] : 0.0f;
                 pvy[it] = (i < bound) ? G.svy[i] : 0.0f;
             }
         }
     };
-    load_chunk(a, b);
+    load_keys(a, b);
+    load_state(a, b);
     const uint32_t kprev = a > 0 ? G.skey[a - 1] : kNone;
     // p0: the first particle in [a, b) whose cell differs from that of the particle before a
     // (keys past b read as kNone, so a wave whose range holds no cell start finds p0 >= b)
@@ -104,7 +117,20 @@ __device__ __forceinline__ void seg_reduce(const GridView& G, uint32_t wave_inde
     uint32_t before_chunk = kNone;  // masked key of the particle before the chunk
 
     for (uint32_t base = a;; base += kSegRange) {
-        if (base != a) load_chunk(base, n);
+        if (base != a) {
+            // past the wave's share only the run of kl continues: its state is read up to the
+            // first particle of another cell
+            load_keys(base, n);
+            uint32_t lend = kSegItems;
+#pragma unroll
+            for (int it = kSegItems - 1; it >= 0; --it)
+                if (key[it] != kl) lend = it;
+            const uint64_t other = __ballot(lend < (uint32_t)kSegItems);
+            const int lo = other ? __ffsll((unsigned long long)other) - 1 : kWave;
+            const uint32_t run_end =
+                lo < kWave ? base + lo * kSegItems + __shfl(lend, lo, kWave) : base + kSegRange;
+            load_state(base, min(run_end, n));
+        }
         const uint32_t i0 = base + lane * kSegItems;
         // particles outside [p0, end of kl's run) and outside the grid take no part
 #pragma unroll

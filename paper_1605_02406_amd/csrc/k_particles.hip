@@ -219,10 +219,10 @@ hipError_t launch_born_offsets(const GridRef* g, int n, hipStream_t s)
 }
 
 // ----------------------------------------------------------------------------------------------
-// One launch, two kinds of tiles: persistent tiles of kResTile particles normalise the sorted
-// weights (Alg. 4, last loop: w <- p_A mu_A g w + (1 - p_A) mu_UA w), new-born tiles of
-// kBornTile slots initialise their slots (Alg. 5); both store the fixed-point sum of their
-// weights for the resampling.
+// One launch, two kinds of blocks: persistent blocks of kPtSplit resampling tiles normalise the
+// sorted weights (Alg. 4, last loop: w <- p_A mu_A g w + (1 - p_A) mu_UA w), new-born tiles of
+// kBornTile slots initialise their slots (Alg. 5); both store the fixed-point weight sum of each
+// resampling tile.
 // ----------------------------------------------------------------------------------------------
 
 __device__ __forceinline__ double likelihood(double vx, double vy, double mx, double my,
@@ -276,20 +276,23 @@ __global__ __launch_bounds__(kResThreads) void k_particle_tiles(Batch b)
     const MeasView M = meas_view(b.m[gi]);
     const uint32_t tile = blockIdx.x - b.bstart[gi];
     const int lane = lane_id(), wave = threadIdx.x / kWave;
+    const uint32_t pblocks = ceil_div_u32(G.n_res_ptiles, kPtSplit);
     uint64_t q = 0;
-    if (tile < G.n_res_ptiles) {
-        uint32_t k[kResItems];
-        float w[kResItems];
+    if (tile < pblocks) {
+        // kPtSplit resampling tiles; items [h * kResItems, (h + 1) * kResItems) lie in tile h
+        uint64_t qh[kPtSplit] = {};
+        uint32_t k[kPtItems];
+        float w[kPtItems];
 #pragma unroll
-        for (int it = 0; it < kResItems; ++it) {
-            const uint32_t i = tile * kResTile + it * kResThreads + threadIdx.x;
+        for (int it = 0; it < kPtItems; ++it) {
+            const uint32_t i = tile * kPtTile + it * kResThreads + threadIdx.x;
             k[it] = i < G.nu ? G.skey[i] : kNoCell;
             w[it] = i < G.nu ? G.sw[i] : 0.0f;
         }
         const bool assoc = static_cast<bool>(M.p_assoc);
 #pragma unroll
-        for (int it = 0; it < kResItems; ++it) {
-            const uint32_t i = tile * kResTile + it * kResThreads + threadIdx.x;
+        for (int it = 0; it < kPtItems; ++it) {
+            const uint32_t i = tile * kPtTile + it * kResThreads + threadIdx.x;
             if (k[it] >= G.C) continue;  // idle lane, or outside the grid (weight 0 already)
             const double wd = (double)w[it];
             double wn;
@@ -305,12 +308,18 @@ __global__ __launch_bounds__(kResThreads) void k_particle_tiles(Batch b)
             }
             const float wf = (float)wn;
             G.sw[i] = wf;
-            q += fixed40(wf);
+            qh[it / kResItems] += fixed40(wf);
+        }
+#pragma unroll
+        for (int h = 0; h < kPtSplit; ++h) {
+            const uint64_t qsum = block_sum(qh[h], tmp);
+            const uint32_t t = tile * kPtSplit + h;
+            if (threadIdx.x == 0 && t < G.n_res_ptiles) G.rpart[t] = qsum;
         }
     } else {
         // new-born slots, one per thread: the cell of a slot is the last mark at or before it,
         // or the tile's first cell if there is none (cells are numbered in slot order)
-        const uint32_t bt = tile - G.n_res_ptiles;
+        const uint32_t bt = tile - pblocks;
         const uint32_t s = bt * kBornTile + threadIdx.x;
         const uint64_t Stot = *G.S_fixed;
         const uint32_t cycle = *G.cycle_run;
@@ -335,16 +344,18 @@ __global__ __launch_bounds__(kResThreads) void k_particle_tiles(Batch b)
                 q = fixed40(init_born(G, M, s, c, cycle));
             }
         }
+        const uint64_t qsum = block_sum(q, tmp);
+        if (threadIdx.x == 0) G.rpart[G.n_res_ptiles + bt] = qsum;
     }
-    const uint64_t qsum = block_sum(q, tmp);
-    if (threadIdx.x == 0) G.rpart[tile] = qsum;
 }
 
 hipError_t launch_particle_tiles(const GridRef* g, int n, hipStream_t s)
 {
     Batch b;
     const uint32_t blocks =
-        make_batch(b, g, n, [](const GridDev& G) { return G.n_res_ptiles + G.n_born_parts; });
+        make_batch(b, g, n, [](const GridDev& G) {
+            return ceil_div(G.n_res_ptiles, kPtSplit) + G.n_born_parts;
+        });
     if (blocks) DOGM_LAUNCH(k_particle_tiles, dim3(blocks), dim3(kResThreads), 0, s, b);
     return hipGetLastError();
 }
