@@ -1,0 +1,45 @@
+"""Filter quality on the synthetic lanes scene (Sec. VIII), through the GPU path: the paper's
+qualitative findings on the birth probability p_B that the synthetic scene reproduces."""
+import pytest
+import torch
+
+from paper_1605_02406_amd import dogm, evaluate
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def results():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    dogm.lib()
+    return {pb: evaluate.evaluate(pb) for pb in (0.005, 0.02, 0.1)}
+
+
+def test_velocity_of_moving_objects_is_estimated(results):
+    r = results[0.02]
+    assert r["samples"] >= 150
+    assert r["velocity_mae_mps"] < 2.0          # objects move at 3 to 8 m/s
+
+
+def test_new_born_particles_bias_the_velocity_towards_zero(results):
+    # the birth velocity distribution has zero mean: more births, more bias (Sec. VIII.A)
+    b = {pb: results[pb]["velocity_bias_along_motion_mps"] for pb in results}
+    assert b[0.1] < b[0.02] - 0.2 and b[0.1] < b[0.005] - 0.2
+    assert all(v < 0 for v in b.values())
+
+
+def test_uncertainty_grows_with_the_birth_probability(results):
+    sd = [results[pb]["velocity_sd_mps"] for pb in (0.005, 0.02, 0.1)]
+    assert sd[0] < sd[1] < sd[2]
+
+
+def test_estimates_are_consistent(results):
+    # NEES of the x-velocity against the 95 % level of chi^2(1) (Sec. VIII.B)
+    for pb, r in results.items():
+        assert r["nees_frac_above_95pct"] < 0.15, pb
+
+
+def test_moving_cells_separate_from_static_ones(results):
+    for pb, r in results.items():
+        assert r["roc_auc"] > 0.75, pb
