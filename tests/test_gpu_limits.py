@@ -1,0 +1,137 @@
+"""Edge cases at the limits of the boundary: the largest particle count it accepts, more grids
+in one batch than one launch holds, and degenerate grid shapes."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1605_02406_amd import dogm, scenes
+from tests.parity import PerCall, device_meas, host, oracle_params, u32, POS_TOL, W_PRED_TOL
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    dogm.lib()
+
+
+def test_largest_particle_count():
+    """nu = 2^28 - 1 (the largest the boundary accepts) on the 1024x1024 grid at 0.1 m with 2^20
+    new-born slots, second cycle: prediction parity on the first 2^20 particles (the oracle's
+    random streams are per particle index), and on all particles the properties every correct
+    result has: a stable sort (a permutation with non-decreasing keys whose cell ranges count
+    the keys), per-cell sums of the sorted weights, the updated persistent mass of each cell
+    equal to rho_p, and uniform weights W / nu after the resampling."""
+    nx = ny = 1024
+    nu, nb, n_chk = (1 << 28) - 1, 1 << 20, 1 << 20
+    C = nx * ny
+    p = dogm.make_params(nx, ny, 0.1, nu, nb, seed=3, **scenes.FILTER)
+    g = dogm.Grid(p)
+    wl = dict(scenes.WORKLOADS["c1024"])
+    seq = [device_meas(m) for m in scenes.measurement_sequence(wl, 2)]
+    print("[limits] cycle 1", flush=True)
+    g.step(seq[0])
+    op = oracle_params(p)
+    k = g.cycle
+    st0 = {c: v[:n_chk].cpu().numpy() for c, v in
+           zip(("x", "y", "vx", "vy", "w"), (g.v["x"], g.v["y"], g.v["vx"], g.v["vy"], g.v["w"]))}
+    print("[limits] cycle 2 predict", flush=True)
+    g.predict()
+    torch.cuda.synchronize()
+    ref, _ = oracle.predict(op, k, st0)
+    for c in ("x", "y", "vx", "vy"):
+        got = g.v[c][:n_chk].cpu().numpy().astype(np.float64)
+        err = np.max(np.abs(got - ref[c]) / np.maximum(np.abs(ref[c]), 1.0))
+        assert err <= POS_TOL, c
+    gw = g.v["w"][:n_chk].cpu().numpy().astype(np.float64)
+    assert np.max(np.abs(gw - ref["w"]) / np.maximum(np.abs(ref["w"]), 1e-30)) <= W_PRED_TOL
+    key_chk = oracle.cell_keys_f32(op, g.v["x"][:n_chk].cpu().numpy(), g.v["y"][:n_chk].cpu().numpy())
+    assert np.array_equal(u32(g.v["key"][:n_chk]), key_chk)
+
+    print("[limits] cycle 2 assign", flush=True)
+    key = g.v["key"].to(torch.int64)
+    g.assign()
+    torch.cuda.synchronize()
+    skey = g.v["skey"].to(torch.int64)
+    perm = g.v["perm"].to(torch.int64)
+    assert bool((skey[1:] >= skey[:-1]).all()), "sorted keys decrease"
+    assert bool((torch.sort(perm).values == torch.arange(nu, device=perm.device)).all())
+    assert bool((key[perm] == skey).all())
+    # stability: equal keys keep their input order
+    same = skey[1:] == skey[:-1]
+    assert bool((perm[1:][same] > perm[:-1][same]).all()), "equal keys out of input order"
+    assert bool((g.v["sw"] == g.v["w"][perm]).all())
+    inside = skey[skey < C]
+    counts = torch.bincount(inside, minlength=C)
+    start = g.v["cell_start"].to(torch.int64)
+    end = g.v["cell_end"].to(torch.int64)
+    assert bool(((end - start) == counts).all())
+    occ = counts > 0
+    first = torch.cumsum(counts, 0) - counts
+    assert bool((start[occ] == first[occ]).all())
+    sums = torch.zeros(C, dtype=torch.float64, device=skey.device)
+    sums.index_add_(0, inside, g.v["sw"][: inside.numel()].to(torch.float64))
+    del key, perm, same, first
+
+    print("[limits] cycle 2 update, moments, resample", flush=True)
+    g.update(seq[1])
+    torch.cuda.synchronize()
+    sum_w = g.v["sum_w"]
+    assert torch.allclose(sum_w[occ], sums[occ], rtol=1e-9, atol=0.0)
+    upd = torch.zeros(C, dtype=torch.float64, device=skey.device)
+    upd.index_add_(0, inside, g.v["sw"][: inside.numel()].to(torch.float64))
+    rho_p = g.v["rho_p"].to(torch.float64)
+    assert torch.allclose(upd[occ], rho_p[occ], rtol=1e-5, atol=1e-12)
+    g.moments()
+    g.resample()
+    torch.cuda.synchronize()
+    assert g.status() == 0
+    W = int(g.v["W_fixed"].item())
+    assert W > 0
+    out_w = np.float32(W * 2.0 ** -40 / nu)
+    assert bool((g.v["w"] == float(out_w)).all())
+
+
+def test_more_grids_than_one_launch_holds():
+    """40 grids in one dogm_step_batch (launches of at most 32 grids) equal each grid alone."""
+    sizes = [(8 + (i % 9), 5 + (i % 7)) for i in range(40)]
+    seqs = []
+    for i, (nx, ny) in enumerate(sizes):
+        wl = dict(nx=nx, ny=ny, cell=0.2, n_pers=6 * nx * ny, n_born=nx * ny, scene="boxes",
+                  n_boxes=1, clutter=0.02, seed=i)
+        seqs.append((wl, [device_meas(m) for m in scenes.measurement_sequence(wl, 2, seed=i)]))
+
+    def params(i, wl):
+        return dogm.make_params(wl["nx"], wl["ny"], wl["cell"], wl["n_pers"], wl["n_born"],
+                                seed=21, grid_id=i, **scenes.FILTER)
+
+    single = []
+    for i, (wl, seq) in enumerate(seqs):
+        g = dogm.Grid(params(i, wl))
+        for m in seq:
+            g.step(m)
+        torch.cuda.synchronize()
+        single.append({k: host(v).copy() for k, v in g.v.items()})
+    grids = [dogm.Grid(params(i, wl)) for i, (wl, _) in enumerate(seqs)]
+    for k in range(2):
+        dogm.step_batch(grids, [seq[k] for _, seq in seqs])
+    torch.cuda.synchronize()
+    for i, (g, ref) in enumerate(zip(grids, single)):
+        for k, v in g.v.items():
+            assert np.array_equal(host(v), ref[k]), (i, k)
+
+
+@pytest.mark.parametrize("nx,ny", [(1, 1), (1, 50), (50, 1), (2, 3)])
+def test_degenerate_grid_shapes(nx, ny):
+    """A single cell, single rows and columns: two cycles of per-call parity from arbitrary
+    particle states (most particles leave such grids)."""
+    p = dogm.make_params(nx, ny, 0.2, 3000, 300, seed=5, grid_id=nx * 100 + ny, **scenes.FILTER)
+    g = dogm.Grid(p)
+    g.load_state(scenes.random_particles(nx, ny, 0.2, 3000, nx + ny, spread=0.3))
+    pc = PerCall(g)
+    for k in range(2):
+        print(f"[parity] grid {nx}x{ny} cycle {k + 1}", flush=True)
+        pc.cycle(device_meas(scenes.random_measurement(nx * ny, 40 + k)))
