@@ -385,6 +385,10 @@ def main():
                      "launch_ms_mean": dom_mean_ms, "launches_timed": len(dom_ms)},
         "status_word": status,
         "meas_generation_s": t_gen,
+        # the assignment (radix sort and per-cell pass) against one ideal pass that reads and
+        # writes a 24-byte record once: 8 TB/s / 48 B
+        "sort": {"keys_per_s": nu / (per_call["assign"] * 1e-3),
+                 "ideal_pass_keys_per_s": HBM_PEAK_GBS * 1e9 / 48.0},
     }
 
     modes = {}
@@ -572,7 +576,14 @@ def cpu_baseline(p, seq, budget_s):
         dt = time.perf_counter() - t0
         if dt >= budget_s:
             break
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((l.split(":", 1)[1].strip() for l in fh if l.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": n / dt, "unit": "cycles/s", "cores": 1, "kind": "oracle",
+            "host_cpu": model, "host_cpus": os.cpu_count(),
             "sample": f"{n} cycles of the same 512x512 / 2^21+2^18 workload from the oracle's "
                       f"own initial state ({dt:.1f} s)",
             "particles_per_s": n * op.n_pers / dt}

@@ -13,6 +13,9 @@
 // peer advances the wave's running count of that digit (16-bit counters in LDS).  Sixteenths are
 // stacked in wave order, so every key's rank is its position among equal digits in input order.
 // The tile is then rearranged in LDS so each digit's run leaves as one contiguous block.
+#include <mutex>
+#include <vector>
+
 #include "launch.h"
 
 namespace dogm {
@@ -308,16 +311,28 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(Batch b, uint32_t
     move_out(pa, A.ow, stage, lpos, gpos);
 }
 
+// The scatter's dynamic LDS (up to 96 KiB with 11-bit digits) is above the default limit: raise
+// it once on every device the library launches on (the attribute is per device).
+hipError_t allow_scatter_lds()
+{
+    static std::mutex mu;
+    static std::vector<bool> done;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lock(mu);
+    if ((size_t)dev < done.size() && done[dev]) return hipSuccess;
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sort_scatter),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
+    if (e != hipSuccess) return e;
+    if ((size_t)dev >= done.size()) done.resize(dev + 1, false);
+    done[dev] = true;
+    return hipSuccess;
+}
+
 hipError_t launch_sort(const GridRef* g, int n, hipStream_t s)
 {
-    static bool lds_limit_set = false;
-    if (!lds_limit_set) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sort_scatter),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           96 * 1024);
-        if (e != hipSuccess) return e;
-        lds_limit_set = true;
-    }
+    if (const hipError_t e = allow_scatter_lds(); e != hipSuccess) return e;
     uint32_t max_passes = 0;
     for (int i = 0; i < n; ++i)
         max_passes = g[i].hd->passes > max_passes ? g[i].hd->passes : max_passes;
