@@ -360,8 +360,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "512x512 grid at 0.2 m, 2^21 persistent + 2^18 new-born "
-                               "particles, ray-cast scene of 30 moving boxes + 1% clutter",
+        "config": {"workload": describe_workload(wl),
                    "nx": wl["nx"], "ny": wl["ny"], "cell_m": wl["cell"], "n_pers": nu,
                    "n_born": nb},
         "particles_per_s": cycles_per_s * nu,
@@ -407,6 +406,17 @@ def main():
         print(f"[bench] oracle on the host, {args.cpu_seconds:.0f} s", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(p, seq, args.cpu_seconds)
     print(json.dumps(out), flush=True)
+
+
+def _pow2(n: int) -> str:
+    return f"2^{n.bit_length() - 1}" if n > 0 and n & (n - 1) == 0 else str(n)
+
+
+def describe_workload(wl: dict) -> str:
+    scene = (f"ray-cast scene of {wl['n_boxes']} moving boxes + {wl['clutter'] * 100:g}% clutter"
+             if wl["scene"] == "boxes" else "ray-cast scene of 3 moving boxes and 2 walls")
+    return (f"{wl['nx']}x{wl['ny']} grid at {wl['cell']:g} m, {_pow2(wl['n_pers'])} persistent + "
+            f"{_pow2(wl['n_born'])} new-born particles, {scene}")
 
 
 def b_alg(nu: int, nb: int, C: int) -> int:
@@ -584,7 +594,8 @@ def cpu_baseline(p, seq, budget_s):
         pass
     return {"value": n / dt, "unit": "cycles/s", "cores": 1, "kind": "oracle",
             "host_cpu": model, "host_cpus": os.cpu_count(),
-            "sample": f"{n} cycles of the same 512x512 / 2^21+2^18 workload from the oracle's "
+            "sample": f"{n} cycles of the same {p.nx}x{p.ny} / {_pow2(p.n_pers)}+{_pow2(p.n_born)} "
+                      f"workload from the oracle's "
                       f"own initial state ({dt:.1f} s)",
             "particles_per_s": n * op.n_pers / dt}
 
