@@ -130,11 +130,15 @@ class Server:
         return True
 
     def close(self, sid):
-        """Ends a stream once its queued and running cycles are done; frees its budget."""
+        """Ends a stream: waits for the batches that still run its cycles (other streams' work is
+        left queued), then frees its grid and its budget."""
+        if sid not in self.grids:
+            raise KeyError(f"stream {sid!r} is not open")
         if self.pending.get(sid):
             raise RuntimeError(f"stream {sid!r} still has pending requests")
-        if any(r.sid == sid for b in self.inflight for r in b.reqs):
-            self.drain()
+        while any(r.sid == sid for b in self.inflight for r in b.reqs):
+            self.inflight[0].event.synchronize()
+            self.poll()
         del self.grids[sid]
         self.admission.release(sid)
 

@@ -90,3 +90,23 @@ def test_admission_refuses_over_budget_and_frees_on_close():
     assert srv.open("small", p_small)
     with pytest.raises(KeyError):
         srv.submit("big", None)
+
+
+def test_close_waits_only_for_the_closed_stream():
+    """Closing a stream with a cycle in flight finishes that cycle and keeps the other streams'
+    queued requests queued."""
+    seqs = _sequences()
+    srv = Server(1 << 34, max_batch=1, max_inflight=2)
+    for i in (0, 1):
+        assert srv.open(i, _params(i, *SIZES[i]))
+    srv.submit(0, seqs[0][0])
+    srv.pump()                      # stream 0 in flight
+    srv.submit(1, seqs[1][0])      # stream 1 queued behind it
+    srv.close(0)
+    assert 0 not in srv.grids and srv.admission.used == dogm.arena_bytes(_params(1, *SIZES[1]))
+    assert [r.sid for r in srv.stats.done] == [0]
+    assert list(srv.pending) == [1]
+    srv.drain()
+    assert [r.sid for r in srv.stats.done] == [0, 1]
+    with pytest.raises(KeyError):
+        srv.close(0)
