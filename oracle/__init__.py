@@ -109,6 +109,8 @@ def lib():
             "or_dempster": (ct.c_int, [ct.c_double] * 4 + [d, d]),
             "or_cell_update": (ct.c_uint32, [P, ct.c_int64, d, u32, u32, d, d, d, d, d, d, d,
                                              d, d, d, d]),
+            "or_cell_update_bayes": (ct.c_uint32, [P, ct.c_int64, d, u32, u32, d, d, d, d, d,
+                                                   d, d, d, d, d, d]),
             "or_velocity_likelihood": (ct.c_double, [ct.c_double] * 5),
             "or_persistent_update": (None, [ct.c_int64, d, d, d, u32, u32, d, d, d, d, d, d,
                                             d]),
@@ -239,6 +241,21 @@ def cell_update(p: Params, w_sorted, start, end, m_free_prev, z_occ, z_free):
                                                     np.uint32),
         _p(np.ascontiguousarray(end, np.uint32), np.uint32), _p(_d(m_free_prev), np.float64),
         _p(_d(z_occ), np.float64), _p(_d(z_free), np.float64),
+        *[_p(outs[k], np.float64) for k in CELL_OUT])
+    outs["status"] = int(st)
+    return outs
+
+
+def cell_update_bayes(p: Params, w_sorted, start, end, p_tp, p_fp, det):
+    """The particle PHD/MIB cell step of Sec. V (p_A = 0): see or_cell_update_bayes."""
+    C = p.C
+    outs = {k: np.zeros(C, np.float64) for k in CELL_OUT}
+    w = _d(w_sorted)
+    st = lib().or_cell_update_bayes(
+        ct.byref(p._c()), C, _p(w, np.float64), _p(np.ascontiguousarray(start, np.uint32),
+                                                    np.uint32),
+        _p(np.ascontiguousarray(end, np.uint32), np.uint32), _p(_d(p_tp), np.float64),
+        _p(_d(p_fp), np.float64), _p(_d(det), np.float64),
         *[_p(outs[k], np.float64) for k in CELL_OUT])
     outs["status"] = int(st)
     return outs
@@ -378,7 +395,10 @@ def cycle(p: Params, k: int, state: dict, m_F, meas: dict):
     pred, key = predict(p, k, state)
     perm, start, end = assign(key, C)
     srt = {kk: pred[kk][perm] for kk in ("x", "y", "vx", "vy", "w")}
-    cu = cell_update(p, srt["w"], start, end, m_F, meas["m_occ"], meas["m_free"])
+    if "det" in meas:  # the particle PHD/MIB filter of Sec. V
+        cu = cell_update_bayes(p, srt["w"], start, end, meas["p_tp"], meas["p_fp"], meas["det"])
+    else:
+        cu = cell_update(p, srt["w"], start, end, m_F, meas["m_occ"], meas["m_free"])
     opt = {kk: meas.get(kk) for kk in ("p_assoc", "mu_vx", "mu_vy", "var_v")}
     w_post, mu_A, mu_UA = persistent_update(C, srt["w"], srt["vx"], srt["vy"], start, end,
                                             cu["rho_p"], **opt)

@@ -292,6 +292,50 @@ uint32_t or_cell_update(const or_params* p, int64_t C, const double* w_sorted,
     return status;
 }
 
+/* The per-cell step of the particle PHD/MIB filter itself (Sec. V), without the Dempster-Shafer
+ * approximation, for p_A = 0: a true positive then has the clutter density as its likelihood,
+ * so every weight in the cell (persistent and new-born) is scaled by the same factor f.
+ *   r_p   = min(sum w, 1)                      eq. (predExistenceProbParticles), truncated
+ *   r_b   = p_B (1 - r_p)                      eq. (pred_birth_prob), in every cell
+ *   r     = r_p + r_b                          predicted existence of the cell
+ *   measurement (det = 1):  f = p_TP / (p_FP (1 - r) + p_TP r)
+ *       eqs. (updateParticleWeightsUnnormalized), (applyNormalization), (normalizationCalculation)
+ *   no measurement:         f = (1 - p_TP) / ((1 - p_TP) r + (1 - p_FP) (1 - r))
+ *       eq. (updateParticleWeightsEmpty)
+ *   rho_p = f r_p, rho_b = f r_b; the posterior occupancy f r, eq. (occupancyProbParticles)
+ * Outputs share the Dempster-Shafer layout: m_pO = r_p, m_pF = 1 - r, m_O = pign = f r,
+ * m_F = 1 - f r.  Returns the status bits. */
+uint32_t or_cell_update_bayes(const or_params* p, int64_t C, const double* w_sorted,
+                              const uint32_t* cell_start, const uint32_t* cell_end,
+                              const double* p_tp, const double* p_fp, const double* det,
+                              double* sum_w, double* m_pO, double* m_pF, double* m_O, double* m_F,
+                              double* rho_b, double* rho_p, double* pign)
+{
+    uint32_t status = 0;
+    for (int64_t c = 0; c < C; ++c) {
+        double s = 0.0;
+        for (uint32_t k = cell_start[c]; k < cell_end[c]; ++k) s += w_sorted[k];
+        const double rp = s < 1.0 ? s : 1.0;
+        const double rb = p->p_b * (1.0 - rp);
+        const double r = rp + rb;
+        double f;
+        if (det[c] != 0.0)
+            f = p_tp[c] / (p_fp[c] * (1.0 - r) + p_tp[c] * r);
+        else
+            f = (1.0 - p_tp[c]) / ((1.0 - p_tp[c]) * r + (1.0 - p_fp[c]) * (1.0 - r));
+        sum_w[c] = s;
+        m_pO[c] = rp;
+        m_pF[c] = 1.0 - r;
+        m_O[c] = f * r;
+        m_F[c] = 1.0 - f * r;
+        rho_b[c] = f * rb;
+        rho_p[c] = f * rp;
+        pign[c] = f * r;
+        if (!isfinite(f) || !isfinite(s)) status |= OR_ST_NONFINITE;
+    }
+    return status;
+}
+
 /* ------------------------------------------------------------------------------------ */
 /* a4: update of persistent particles (eqs. (DSupdateParticleWeightsUnnormalized) to     */
 /*     (DSnormalizationfactor2), Alg. 4)                                                 */
