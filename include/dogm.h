@@ -72,8 +72,22 @@ typedef struct dogm_params {
     int64_t n_born;        /* new-born slots nu_b, 0 <= nu_b < 2^30                         */
     uint64_t seed;         /* Philox4x32-10 key                                            */
     uint32_t grid_id;      /* fourth Philox counter word: separates grids with one seed     */
-    uint32_t reserved;     /* must be 0                                                     */
+    uint32_t model;        /* DOGM_MODEL_DS (0) or DOGM_MODEL_PHD_MIB (1), see below        */
 } dogm_params;
+
+/* The per-cell step of the filter.
+ *  DOGM_MODEL_DS: the Dempster-Shafer approximation of Sec. VI (eqs. (DS_particle_sum_pred) to
+ *    (DS_resulting_masses1/2)); measurements are the BBA m_occ, m_free; new-born mass only in
+ *    cells with m_z(O) > 0.
+ *  DOGM_MODEL_PHD_MIB: the particle PHD/MIB filter of Sec. V without that approximation, with
+ *    p_A = 0: per cell r_p = min(sum w, 1), r_b = p_B (1 - r_p) (every cell), r = r_p + r_b,
+ *    and every weight is scaled by f = p_TP / (p_FP (1 - r) + p_TP r) after a measurement
+ *    (eqs. (updateParticleWeightsUnnormalized), (applyNormalization),
+ *    (normalizationCalculation)) or by f = (1 - p_TP) / ((1 - p_TP) r + (1 - p_FP) (1 - r))
+ *    without one (eq. (updateParticleWeightsEmpty)); rho_p = f r_p, rho_b = f r_b.  The cell
+ *    outputs keep the layout of the first model: m_pO = r_p, m_pF = 1 - r, m_O = pign = f r,
+ *    m_F = 1 - f r.  Measurements are p_tp, p_fp and det; alpha_free is not used. */
+enum { DOGM_MODEL_DS = 0, DOGM_MODEL_PHD_MIB = 1 };
 
 /* One measurement grid (Sec. VI.C): device pointers to C floats each, read only during the
  * dogm_update / dogm_step call's kernels.  m_occ, m_free: the observed BBA m_z(O), m_z(F)
@@ -83,7 +97,12 @@ typedef struct dogm_params {
  * new-born velocity pdf, and must be non-NULL.
  * In this build velocity evidence is switched off: a non-NULL p_assoc makes dogm_update,
  * dogm_step and dogm_step_batch return DOGM_ENOTIMPL before anything is enqueued (the text
- * from dogm_status_string / dogm_last_error says so). */
+ * from dogm_status_string / dogm_last_error says so).
+ * For a grid of DOGM_MODEL_PHD_MIB (Sec. V.C observation process) p_tp, p_fp and det are
+ * required instead of m_occ, m_free (which are not read) and p_assoc must be NULL: p_tp, p_fp
+ * are the true and false positive probabilities of the cell in [0, 1] (equal where the cell is
+ * not observed, which then keeps its prediction), det is 1 where a measurement occurred and 0
+ * elsewhere.  DOGM_EINVAL otherwise. */
 typedef struct dogm_meas {
     const float* m_occ;
     const float* m_free;
@@ -91,6 +110,9 @@ typedef struct dogm_meas {
     const float* mu_vx;
     const float* mu_vy;
     const float* var_v;
+    const float* p_tp;
+    const float* p_fp;
+    const float* det;
 } dogm_meas;
 
 /* Device pointers to every array of a grid (all inside the arena). */

@@ -54,7 +54,7 @@ bool valid_params(const dogm_params* p)
     if (!finite_in(p->alpha_free, 0.0f, 1.0f)) return false;
     if (p->n_pers < 1 || p->n_pers >= (int64_t(1) << 28)) return false;
     if (p->n_born < 0 || p->n_born >= (int64_t(1) << 30)) return false;
-    if (p->reserved != 0) return false;
+    if (p->model != DOGM_MODEL_DS && p->model != DOGM_MODEL_PHD_MIB) return false;
     return true;
 }
 
@@ -98,6 +98,7 @@ GridDev describe(const dogm_params* p, char* base, size_t* bytes)
     d.seed_lo = (uint32_t)p->seed;
     d.seed_hi = (uint32_t)(p->seed >> 32);
     d.grid_id = p->grid_id;
+    d.model = p->model;
     // radix digits: as few passes of at most kSortBits bits as cover the largest key (C)
     const int kb = key_bits(C);
     d.passes = (uint32_t)((kb + kSortBits - 1) / kSortBits);
@@ -187,9 +188,13 @@ int evidence_refused(const char* where)
     return DOGM_ENOTIMPL;
 }
 
-bool valid_meas(const dogm_meas* m)
+static_assert(kModelPhdMib == DOGM_MODEL_PHD_MIB, "one model numbering");
+
+bool valid_meas(const dogm_meas* m, uint32_t model)
 {
-    if (!m || !m->m_occ || !m->m_free) return false;
+    if (!m) return false;
+    if (model == DOGM_MODEL_PHD_MIB) return m->p_tp && m->p_fp && m->det && !m->p_assoc;
+    if (!m->m_occ || !m->m_free) return false;
     if (m->p_assoc && (!m->mu_vx || !m->mu_vy || !m->var_v)) return false;
     return true;
 }
@@ -204,6 +209,9 @@ MeasDev to_dev(const dogm_meas* m)
         d.mu_vx = m->mu_vx;
         d.mu_vy = m->mu_vy;
         d.var_v = m->var_v;
+        d.p_tp = m->p_tp;
+        d.p_fp = m->p_fp;
+        d.det = m->det;
     }
     return d;
 }
@@ -376,7 +384,7 @@ int dogm_assign(dogm_grid* grid)
 
 int dogm_update(dogm_grid* grid, const dogm_meas* meas)
 {
-    if (!grid || !valid_meas(meas)) return DOGM_EINVAL;
+    if (!grid || !valid_meas(meas, grid->p.model)) return DOGM_EINVAL;
     if (meas->p_assoc && !evidence_enabled()) return evidence_refused("dogm_update");
     if (grid->phase != kAssigned) return DOGM_ESTATE;
     const GridRef r = grid->ref(meas);
@@ -413,7 +421,7 @@ int dogm_resample(dogm_grid* grid)
 
 int dogm_step(dogm_grid* grid, const dogm_meas* meas)
 {
-    if (!grid || !valid_meas(meas)) return DOGM_EINVAL;
+    if (!grid || !valid_meas(meas, grid->p.model)) return DOGM_EINVAL;
     if (meas->p_assoc && !evidence_enabled()) return evidence_refused("dogm_step");
     if (grid->phase != kReady) return DOGM_ESTATE;
     int rc = dogm_predict(grid);
@@ -428,7 +436,7 @@ int dogm_step_batch(dogm_grid* const* grids, const dogm_meas* meas, int n, dogm_
 {
     if (n < 0 || (n > 0 && (!grids || !meas))) return DOGM_EINVAL;
     for (int i = 0; i < n; ++i) {
-        if (!grids[i] || !valid_meas(&meas[i])) return DOGM_EINVAL;
+        if (!grids[i] || !valid_meas(&meas[i], grids[i]->p.model)) return DOGM_EINVAL;
         if (meas[i].p_assoc && !evidence_enabled()) return evidence_refused("dogm_step_batch");
         if (grids[i]->phase != kReady) return DOGM_ESTATE;
         for (int j = 0; j < i; ++j)

@@ -20,6 +20,7 @@ constexpr int kMaxBatch = 32;
 constexpr int kWave = 64;
 
 // Philox counter word 2: what a draw is for.
+constexpr uint32_t kModelPhdMib = 1;  // the particle PHD/MIB model of Sec. V (else Sec. VI)
 constexpr uint32_t kPurposeInit = 0, kPurposePredict = 1, kPurposeBirth = 2,
                    kPurposeResample = 3;
 
@@ -113,6 +114,7 @@ struct GridT {
     uint32_t C, nu, nb;
     float r, dt, p_s, p_b, sig_pos, sig_vel, sig_birth, alpha;
     uint32_t seed_lo, seed_hi, grid_id;
+    uint32_t model;  // kModelPhdMib: Sec. V; otherwise the Dempster-Shafer model of Sec. VI
     // sort plan (from the largest key, C) and tilings
     uint32_t passes;
     uint32_t dshift[kMaxPasses], dbits[kMaxPasses];
@@ -162,6 +164,7 @@ static_assert(sizeof(GridDev) == sizeof(GridView), "one layout for both pointer 
 template <template <typename> class P>
 struct MeasT {
     P<const float> m_occ, m_free, p_assoc, mu_vx, mu_vy, var_v;
+    P<const float> p_tp, p_fp, det;  // the particle PHD/MIB model's observation (Sec. V.C)
 };
 using MeasDev = MeasT<HostPtr>;
 using MeasView = MeasT<GArr>;
@@ -173,6 +176,7 @@ struct Batch {
     const GridDev* g[kMaxBatch];
     MeasDev m[kMaxBatch];
 };
+static_assert(sizeof(Batch) <= 4096, "a batch descriptor is one kernel argument");
 
 // Private copies of a grid's descriptor and measurement with global-address-space pointers.
 // The descriptor is read through the constant address space (it is never written while a

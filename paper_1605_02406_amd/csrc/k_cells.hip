@@ -249,9 +249,39 @@ __device__ __forceinline__ double likelihood(double vx, double vy, double mx, do
 // (DS_resulting_masses1/2), new-born mass only where m_z(O) > 0) and the normalisation
 // components (eqs. (DSnormalizationfactor), (DSnormalizationfactor2)).  s = sum of predicted
 // weights, st = sum of g w.  Returns rho_p; *rb_out gets the stored rho_b.
+// The particle PHD/MIB model (Sec. V, p_A = 0), FP64: predicted existence r = r_p + r_b with
+// r_p = min(s, 1) (eq. (predExistenceProbParticles), truncated) and r_b = p_B (1 - r_p) (eq.
+// (pred_birth_prob)); every weight of the cell is scaled by the factor of eqs.
+// (updateParticleWeightsUnnormalized), (applyNormalization), (normalizationCalculation) after a
+// measurement, of eq. (updateParticleWeightsEmpty) without one.  Same outputs as cell_update.
+__device__ __forceinline__ double cell_update_phd(const GridView& G, const MeasView& M,
+                                                  uint32_t c, double s, float* rb_out)
+{
+    const double rp = s < 1.0 ? s : 1.0;
+    const double rb_pred = (double)G.p_b * (1.0 - rp);
+    const double r = rp + rb_pred;
+    const double tp = (double)M.p_tp[c], fp = (double)M.p_fp[c];
+    const double f = M.det[c] != 0.0f ? tp / (fp * (1.0 - r) + tp * r)
+                                      : (1.0 - tp) / ((1.0 - tp) * r + (1.0 - fp) * (1.0 - r));
+    const double o = f * r, rho_p = f * rp, rb = f * rb_pred;
+    if (!isfinite(f) || !isfinite(s)) status_or(G, kStNonFinite);
+    G.m_pO[c] = (float)rp;
+    G.m_pF[c] = (float)(1.0 - r);
+    G.m_O[c] = (float)o;
+    G.m_F[c] = (float)(1.0 - o);
+    G.rho_b[c] = (float)rb;
+    G.rho_p[c] = (float)rho_p;
+    G.pign[c] = (float)o;
+    G.mu_UA[c] = s > 0.0 ? rho_p / s : 0.0;
+    G.mu_A[c] = G.mu_UA[c];
+    *rb_out = (float)rb;
+    return rho_p;
+}
+
 __device__ __forceinline__ double cell_update(const GridView& G, const MeasView& M, uint32_t c,
                                               double s, double st, float* rb_out)
 {
+    if (G.model == kModelPhdMib) return cell_update_phd(G, M, c, s, rb_out);
     const double po = s < 1.0 ? s : 1.0;
     const double pf_cand = (double)G.alpha * (double)G.m_F[c];
     const double pf = pf_cand < 1.0 - po ? pf_cand : 1.0 - po;

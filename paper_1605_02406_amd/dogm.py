@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libdogm.so")
 
 DOGM_OK, DOGM_EINVAL, DOGM_ESIZE, DOGM_EHIP, DOGM_ESTATE, DOGM_ENOTIMPL = 0, -1, -2, -3, -4, -5
 ST_CONFLICT, ST_NOCARRIER, ST_NONFINITE, ST_INTERNAL = 1, 2, 4, 8
+MODEL_DS, MODEL_PHD_MIB = 0, 1  # Sec. VI (Dempster-Shafer), Sec. V (particle PHD/MIB)
 
 # Names of the functions include/dogm.h declares.
 ABI = ["dogm_arena_bytes", "dogm_init_grid", "dogm_destroy", "dogm_set_stream", "dogm_set_cycle",
@@ -36,12 +37,12 @@ class CParams(ct.Structure):
                 ("sigma_pos", ct.c_float), ("sigma_vel", ct.c_float),
                 ("sigma_birth_vel", ct.c_float), ("alpha_free", ct.c_float),
                 ("n_pers", ct.c_int64), ("n_born", ct.c_int64), ("seed", ct.c_uint64),
-                ("grid_id", ct.c_uint32), ("reserved", ct.c_uint32)]
+                ("grid_id", ct.c_uint32), ("model", ct.c_uint32)]
 
 
 class CMeas(ct.Structure):
     _fields_ = [(k, ct.c_void_p) for k in ("m_occ", "m_free", "p_assoc", "mu_vx", "mu_vy",
-                                          "var_v")]
+                                          "var_v", "p_tp", "p_fp", "det")]
 
 
 _VIEW_ARRAYS = [  # (name, dtype, length kind)
@@ -115,9 +116,10 @@ def _check(code: int, what: str):
 
 
 def make_params(nx, ny, cell_size, n_pers, n_born, dt=0.1, p_s=0.99, p_b=0.02, sigma_pos=0.1,
-                sigma_vel=0.5, sigma_birth_vel=4.0, alpha_free=0.9, seed=0, grid_id=0) -> CParams:
+                sigma_vel=0.5, sigma_birth_vel=4.0, alpha_free=0.9, seed=0, grid_id=0,
+                model=MODEL_DS) -> CParams:
     return CParams(nx, ny, cell_size, dt, p_s, p_b, sigma_pos, sigma_vel, sigma_birth_vel,
-                   alpha_free, n_pers, n_born, seed, grid_id, 0)
+                   alpha_free, n_pers, n_born, seed, grid_id, model)
 
 
 def arena_bytes(p: CParams) -> int:
@@ -132,11 +134,14 @@ def _stream_ptr(stream) -> int:
 
 
 class Meas:
-    """A measurement grid of device tensors (float32, C each)."""
+    """A measurement grid of device tensors (float32, C each): m_occ, m_free (and the optional
+    velocity evidence) for the Dempster-Shafer model; p_tp, p_fp, det for the particle PHD/MIB
+    model (Sec. V)."""
 
-    def __init__(self, m_occ, m_free, p_assoc=None, mu_vx=None, mu_vy=None, var_v=None):
+    def __init__(self, m_occ=None, m_free=None, p_assoc=None, mu_vx=None, mu_vy=None,
+                 var_v=None, p_tp=None, p_fp=None, det=None):
         self.t = dict(m_occ=m_occ, m_free=m_free, p_assoc=p_assoc, mu_vx=mu_vx, mu_vy=mu_vy,
-                      var_v=var_v)
+                      var_v=var_v, p_tp=p_tp, p_fp=p_fp, det=det)
         for k, v in self.t.items():
             if v is not None:
                 assert v.dtype == torch.float32 and v.is_cuda and v.is_contiguous(), k

@@ -228,9 +228,23 @@ def measurement_grid(occ: np.ndarray, rng: np.random.Generator, p_d=SENSOR["p_d"
     return m_occ, m_free
 
 
+def detection_grid(occ: np.ndarray, rng: np.random.Generator, p_d=SENSOR["p_d"],
+                   p_cl=SENSOR["p_cl"]):
+    """The observation of the particle PHD/MIB model (Sec. V.C) for one cycle, float32 [ny*nx]
+    each: true / false positive probabilities p_tp = p_d, p_fp = p_cl where the cell is seen
+    and 0.5 for both where it is not (no information), and the detection flag det (the same
+    draws as measurement_grid)."""
+    seen = raycast_observed(occ)
+    det = np.where(occ, rng.random(occ.shape) < p_d, rng.random(occ.shape) < p_cl) & seen
+    p_tp = np.where(seen, p_d, 0.5).astype(np.float32).reshape(-1)
+    p_fp = np.where(seen, p_cl, 0.5).astype(np.float32).reshape(-1)
+    return dict(p_tp=p_tp, p_fp=p_fp, det=det.astype(np.float32).reshape(-1))
+
+
 def measurement_sequence(wl: dict, n_cycles: int, seed: int | None = None,
-                         with_truth: bool = False):
-    """Measurement grids for cycles 1..n_cycles of the workload's scene."""
+                         with_truth: bool = False, model: str = "ds"):
+    """Measurement grids for cycles 1..n_cycles of the workload's scene: Dempster-Shafer masses
+    (model "ds") or the detection observation of the particle PHD/MIB model (model "phd")."""
     seed = wl.get("seed", 0) if seed is None else seed
     scene = make_scene(wl, seed)
     out = []
@@ -238,8 +252,11 @@ def measurement_sequence(wl: dict, n_cycles: int, seed: int | None = None,
         scene.advance()
         occ = scene.truth()
         rng = np.random.default_rng(np.random.SeedSequence([seed, k, 99]))
-        m_occ, m_free = measurement_grid(occ, rng)
-        item = dict(m_occ=m_occ, m_free=m_free)
+        if model == "phd":
+            item = detection_grid(occ, rng)
+        else:
+            m_occ, m_free = measurement_grid(occ, rng)
+            item = dict(m_occ=m_occ, m_free=m_free)
         if with_truth:
             vx, vy = scene.velocity_truth()
             item.update(occ=occ.reshape(-1), vx=vx.reshape(-1), vy=vy.reshape(-1))

@@ -132,7 +132,10 @@ class PerCall:
         mz = meas_numpy(meas)
         g.update(meas)
         torch.cuda.synchronize()
-        cu = oracle.cell_update(p, srt["w"], start, end, m_F_prev, mz["m_occ"], mz["m_free"])
+        if g.params.model == dogm.MODEL_PHD_MIB:
+            cu = oracle.cell_update_bayes(p, srt["w"], start, end, mz["p_tp"], mz["p_fp"], mz["det"])
+        else:
+            cu = oracle.cell_update(p, srt["w"], start, end, m_F_prev, mz["m_occ"], mz["m_free"])
         for c in ("m_pO", "m_pF", "m_O", "m_F", "rho_b", "rho_p", "pign"):
             self.stats[f"update.{c}"] = assert_close(f"update {c}", host(g.v[c]), cu[c],
                                                      MASS_TOL, 1e-4)
@@ -207,6 +210,5 @@ class PerCall:
 def device_meas(m: dict, device="cuda") -> dogm.Meas:
     t = {k: (torch.as_tensor(np.ascontiguousarray(v, np.float32), device=device)
              if v is not None else None) for k, v in m.items()
-         if k in ("m_occ", "m_free", "p_assoc", "mu_vx", "mu_vy", "var_v")}
-    return dogm.Meas(t["m_occ"], t["m_free"], t.get("p_assoc"), t.get("mu_vx"), t.get("mu_vy"),
-                     t.get("var_v"))
+         if k in ("m_occ", "m_free", "p_assoc", "mu_vx", "mu_vy", "var_v", "p_tp", "p_fp", "det")}
+    return dogm.Meas(**t)

@@ -67,9 +67,11 @@ def test_arena_bytes_and_validation(dl):
             dl.arena_bytes(q)
         assert e.value.code == dl.DOGM_EINVAL
     q = dl.make_params(64, 64, 0.2, 10, 0)
-    q.reserved = 1
+    q.model = 2  # neither the Dempster-Shafer nor the particle PHD/MIB model
     with pytest.raises(dl.DogmError):
         dl.arena_bytes(q)
+    q.model = dl.MODEL_PHD_MIB
+    assert dl.arena_bytes(q) > 0
 
 
 def test_null_handles_are_rejected(dl):
