@@ -207,6 +207,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="c512")
+    ap.add_argument("--model", choices=("ds", "phd"), default="ds",
+                    help="per-cell step: Dempster-Shafer (Sec. VI) or particle PHD/MIB (Sec. V)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="host time budget of the oracle's CPU baseline: whole cycles are run "
                          "until it is spent (0: skip)")
@@ -246,17 +248,18 @@ def main():
 
     wl = scenes.WORKLOADS[args.workload]
     p = dogm.make_params(wl["nx"], wl["ny"], wl["cell"], wl["n_pers"], wl["n_born"],
-                         seed=wl.get("seed", 0), **scenes.FILTER)
+                         seed=wl.get("seed", 0),
+                         model=dogm.MODEL_PHD_MIB if args.model == "phd" else dogm.MODEL_DS,
+                         **scenes.FILTER)
     C = wl["nx"] * wl["ny"]
     nu, nb = wl["n_pers"], wl["n_born"]
     n_cycles = args.warmup + 2 * args.steps
     print(f"[bench] generating {n_cycles} measurement grids", file=sys.stderr, flush=True)
     t_gen = time.perf_counter()
-    seq = scenes.measurement_sequence(wl, n_cycles)
+    seq = scenes.measurement_sequence(wl, n_cycles, model=args.model)
     t_gen = time.perf_counter() - t_gen
     dev = torch.device("cuda:0")
-    meas = [dogm.Meas(torch.as_tensor(m["m_occ"], device=dev),
-                      torch.as_tensor(m["m_free"], device=dev)) for m in seq]
+    meas = [dogm.Meas(**{k: torch.as_tensor(v, device=dev) for k, v in m.items()}) for m in seq]
     g = dogm.Grid(p)
     torch.cuda.synchronize()
 
@@ -360,7 +363,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": describe_workload(wl),
+        "config": {"workload": describe_workload(wl) + (
+                       "; particle PHD/MIB model (Sec. V)" if args.model == "phd" else ""),
                    "nx": wl["nx"], "ny": wl["ny"], "cell_m": wl["cell"], "n_pers": nu,
                    "n_born": nb},
         "particles_per_s": cycles_per_s * nu,
