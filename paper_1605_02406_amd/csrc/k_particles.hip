@@ -197,6 +197,7 @@ __global__ __launch_bounds__(kCellThreads) void k_born_offsets(Batch b)
     uint32_t o = 0;
     if (Stot != 0) o = (c == G.C) ? G.nb : slot_offset(E, Stot, G.nb);
     G.born_off[c] = o;
+    bool no_carrier = false;
     if (c < G.C && Stot != 0 && G.nb > 0 && q != 0) {
         const uint32_t o1 = (c + 1 == G.C) ? G.nb : slot_offset(E + q, Stot, G.nb);
         if (o1 > o) {
@@ -204,9 +205,12 @@ __global__ __launch_bounds__(kCellThreads) void k_born_offsets(Batch b)
             for (uint32_t t = ceil_div_dev(o, kBornTile); t * (uint32_t)kBornTile < o1; ++t)
                 G.tile_first[t] = c;
         } else {
-            status_or(G, kStNoCarrier);
+            no_carrier = true;
         }
     }
+    // one status update per wave: many cells may lack a slot (with births in every cell)
+    const uint64_t nc = __ballot(no_carrier);
+    if (nc != 0 && lane_id() == __ffsll((unsigned long long)nc) - 1) status_or(G, kStNoCarrier);
 }
 
 hipError_t launch_born_offsets(const GridRef* g, int n, hipStream_t s)
