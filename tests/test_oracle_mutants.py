@@ -10,7 +10,7 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "dogm_oracle.c")
 PIN_SUITES = ["tests/test_oracle_rng.py", "tests/test_oracle_steps.py",
-              "tests/test_oracle_recursion.py"]
+              "tests/test_oracle_recursion.py", "tests/test_oracle_bayes.py"]
 
 MUTANTS = {
     "predict_uses_vy_for_x": ("p->dt * vx[i] + p->sigma_pos * nz[0]",
@@ -37,6 +37,14 @@ MUTANTS = {
     "resample_off_by_one": ("while (i < N && F[i] <= t) ++i;", "while (i < N && F[i] < t) ++i;"),
     "resample_weight_wrong_count": ("return (double)W_fixed * 0x1p-40 / (double)nu;",
                                     "return (double)W_fixed * 0x1p-40 / (double)(nu + 1);"),
+    # the particle PHD/MIB cell step (Sec. V)
+    "phd_births_dropped": ("const double rb = p->p_b * (1.0 - rp);", "const double rb = 0.0;"),
+    "phd_detection_tp_fp_swapped": ("f = p_tp[c] / (p_fp[c] * (1.0 - r) + p_tp[c] * r);",
+                                    "f = p_fp[c] / (p_tp[c] * (1.0 - r) + p_fp[c] * r);"),
+    "phd_miss_wrong_complement": ("((1.0 - p_tp[c]) * r + (1.0 - p_fp[c]) * (1.0 - r))",
+                                  "((1.0 - p_tp[c]) * r + (1.0 - p_fp[c]) * r)"),
+    "phd_no_truncation": ("const double rp = s < 1.0 ? s : 1.0;", "const double rp = s;"),
+    "phd_rho_p_unscaled": ("rho_p[c] = f * rp;", "rho_p[c] = rp;"),
 }
 
 
