@@ -20,7 +20,7 @@ Readings where the paper leaves a choice (each also in the design notes):
     beside it;
   * the x-axis is the driving direction, so the x-components are evaluated as in the paper.
 
-    python -m paper_1605_02406_amd.evaluate [--cycles N] [--p-b 0.005,0.02,0.1]
+    python -m paper_1605_02406_amd.evaluate [--cycles N] [--p-b 0.005,0.02,0.1] [--model ds,phd]
 """
 from __future__ import annotations
 
@@ -128,9 +128,10 @@ def _box_cells(sc: scenes.Scene, b: scenes.Box) -> np.ndarray:
 # -- the run ----------------------------------------------------------------------------------
 
 def evaluate(p_b: float, cycles: int = 80, warmup: int = 20, n_pers: int = 1 << 19,
-             n_born: int = 1 << 16, seed: int = 0) -> dict:
-    """Runs the GPU filter on the lanes scene for `cycles` cycles and returns the metrics over
-    the cycles after `warmup`."""
+             n_born: int = 1 << 16, seed: int = 0, model: str = "ds") -> dict:
+    """Runs the GPU filter (the Dempster-Shafer model, "ds", or the particle PHD/MIB model of
+    Sec. V, "phd") on the lanes scene for `cycles` cycles and returns the metrics over the
+    cycles after `warmup`."""
     import torch
 
     from . import dogm
@@ -138,7 +139,8 @@ def evaluate(p_b: float, cycles: int = 80, warmup: int = 20, n_pers: int = 1 << 
     sc = lanes_scene(seed=seed)
     filt = dict(scenes.FILTER)
     filt["p_b"] = p_b
-    p = dogm.make_params(sc.nx, sc.ny, sc.cell, n_pers, n_born, seed=seed, **filt)
+    p = dogm.make_params(sc.nx, sc.ny, sc.cell, n_pers, n_born, seed=seed,
+                         model=dogm.MODEL_PHD_MIB if model == "phd" else dogm.MODEL_DS, **filt)
     g = dogm.Grid(p)
     moving = [b for b in sc.boxes if b.vx != 0.0 or b.vy != 0.0]
     rows, scores, labels, counts, pigns = [], [], [], [], []
@@ -146,8 +148,12 @@ def evaluate(p_b: float, cycles: int = 80, warmup: int = 20, n_pers: int = 1 << 
         sc.advance()
         occ = sc.truth().reshape(-1)
         rng = np.random.default_rng(np.random.SeedSequence([seed, k, 99]))
-        m_occ, m_free = scenes.measurement_grid(occ.reshape(sc.ny, sc.nx), rng)
-        meas = dogm.Meas(torch.as_tensor(m_occ, device="cuda"), torch.as_tensor(m_free, device="cuda"))
+        if model == "phd":
+            obs = scenes.detection_grid(occ.reshape(sc.ny, sc.nx), rng)
+        else:
+            m_occ, m_free = scenes.measurement_grid(occ.reshape(sc.ny, sc.nx), rng)
+            obs = dict(m_occ=m_occ, m_free=m_free)
+        meas = dogm.Meas(**{k: torch.as_tensor(v, device="cuda") for k, v in obs.items()})
         g.step(meas)
         if k <= warmup:
             continue
@@ -176,7 +182,9 @@ def evaluate(p_b: float, cycles: int = 80, warmup: int = 20, n_pers: int = 1 << 
         labels.append(dyn[occ])
         counts.append(count[occ])
         pigns.append(pign[occ])
-    if g.status() != 0:
+    # births in every cell (Sec. V) leave cells without a slot: not an error there
+    allowed = dogm.ST_NOCARRIER if model == "phd" else 0
+    if g.status() & ~allowed:
         raise RuntimeError(f"filter status word {g.status():#x}")
     score, label = np.concatenate(scores), np.concatenate(labels)
     count, pign = np.concatenate(counts), np.concatenate(pigns)
@@ -194,7 +202,7 @@ def evaluate(p_b: float, cycles: int = 80, warmup: int = 20, n_pers: int = 1 << 
     toward = np.array([(r["est"] - r["truth"]) * math.copysign(1.0, r["truth"]) for r in rows])
     nv = np.array([r["nees"] for r in rows])
     sd = np.sqrt(np.array([r["var"] for r in rows]))
-    return {"p_b": p_b, "cycles": cycles, "warmup": warmup, "samples": len(rows),
+    return {"model": model, "p_b": p_b, "cycles": cycles, "warmup": warmup, "samples": len(rows),
             "velocity_mae_mps": float(np.mean(np.abs(err))),
             "velocity_bias_along_motion_mps": float(np.mean(toward)),
             "velocity_sd_mps": float(np.mean(sd)),
@@ -211,9 +219,11 @@ def main():
     ap.add_argument("--cycles", type=int, default=80)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--p-b", default="0.005,0.02,0.1")
+    ap.add_argument("--model", default="ds,phd", help="ds, phd or both")
     args = ap.parse_args()
-    for pb in [float(x) for x in args.p_b.split(",") if x]:
-        print(json.dumps(evaluate(pb, args.cycles, args.warmup)), flush=True)
+    for model in [m for m in args.model.split(",") if m]:
+        for pb in [float(x) for x in args.p_b.split(",") if x]:
+            print(json.dumps(evaluate(pb, args.cycles, args.warmup, model=model)), flush=True)
 
 
 if __name__ == "__main__":
