@@ -148,8 +148,8 @@ GridDev describe(const dogm_params* p, char* base, size_t* bytes)
     const size_t o_mark = L.take(f_nb);
     const size_t o_rpart = L.take(8ull * (d.n_res_ptiles + d.n_born_parts));
     const size_t o_tfirst = L.take(4ull * d.n_born_parts);
-    const size_t o_cyc = L.take(4), o_cycr = L.take(4), o_st = L.take(4), o_W = L.take(8),
-                 o_S = L.take(8);
+    const size_t o_cyc = L.take(4), o_cycr = L.take(4), o_st = L.take(4), o_nc = L.take(4),
+                 o_W = L.take(8), o_S = L.take(8);
     *bytes = L.total;
     if (!base) return d;
 
@@ -173,6 +173,7 @@ GridDev describe(const dogm_params* p, char* base, size_t* bytes)
     d.cycle = at<uint32_t>(base, o_cyc);
     d.cycle_run = at<uint32_t>(base, o_cycr);
     d.status = at<uint32_t>(base, o_st);
+    d.nc_flag = at<uint32_t>(base, o_nc);
     d.W_fixed = at<uint64_t>(base, o_W);
     d.S_fixed = at<uint64_t>(base, o_S);
     return d;

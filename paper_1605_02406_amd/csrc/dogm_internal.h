@@ -154,6 +154,7 @@ struct GridT {
     P<uint32_t> cycle;
     P<uint32_t> cycle_run;
     P<uint32_t> status;
+    P<uint32_t> nc_flag;  // kStNoCarrier once any cell lacked a slot (plain stores, sticky)
     P<uint64_t> W_fixed;
     P<uint64_t> S_fixed;
 };

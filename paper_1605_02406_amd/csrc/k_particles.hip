@@ -37,6 +37,7 @@ __global__ __launch_bounds__(kElemThreads) void k_init(Batch b)
         *G.cycle = 1u;
         *G.cycle_run = 1u;
         *G.status = 0u;
+        *G.nc_flag = 0u;
         *G.W_fixed = 0;
         *G.S_fixed = 0;
     }
@@ -208,9 +209,11 @@ __global__ __launch_bounds__(kCellThreads) void k_born_offsets(Batch b)
             no_carrier = true;
         }
     }
-    // one status update per wave: many cells may lack a slot (with births in every cell)
+    // With births in every cell most waves may hold a cell without a slot.  Device-scope atomics
+    // on one word serialise across the whole chip (about 12 ns each), so such waves store the
+    // same constant into a flag word instead; the next launch folds it into the status.
     const uint64_t nc = __ballot(no_carrier);
-    if (nc != 0 && lane_id() == __ffsll((unsigned long long)nc) - 1) status_or(G, kStNoCarrier);
+    if (nc != 0 && lane_id() == __ffsll((unsigned long long)nc) - 1) *G.nc_flag = kStNoCarrier;
 }
 
 hipError_t launch_born_offsets(const GridRef* g, int n, hipStream_t s)
@@ -281,6 +284,7 @@ __global__ __launch_bounds__(kResThreads) void k_particle_tiles(Batch b)
     const uint32_t tile = blockIdx.x - b.bstart[gi];
     const int lane = lane_id(), wave = threadIdx.x / kWave;
     const uint32_t pblocks = ceil_div_u32(G.n_res_ptiles, kPtSplit);
+    if (tile == 0 && threadIdx.x == 0 && *G.nc_flag != 0u) status_or(G, kStNoCarrier);
     uint64_t q = 0;
     if (tile < pblocks) {
         // kPtSplit resampling tiles; items [h * kResItems, (h + 1) * kResItems) lie in tile h

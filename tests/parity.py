@@ -79,6 +79,10 @@ class PerCall:
         self.g = grid
         self.p = oracle_params(grid.params)
         self.stats = {}
+        # the no-carrier status bit is sticky: its value is known only while every update since
+        # the first cycle was checked here
+        self.nocarrier = 0
+        self.k_seen = 0
 
     def predict(self):
         g, p = self.g, self.p
@@ -158,6 +162,19 @@ class PerCall:
         for c, n in (("x", "bx"), ("y", "by"), ("vx", "bvx"), ("vy", "bvy")):
             self.stats[f"born.{c}"] = assert_close(f"born {c}", host(g.v[n]), b[c], POS_TOL, 1.0)
         self.stats["born.w"] = assert_close("born w", host(g.v["bw"]), b["w"], W_TOL, 1e-12)
+        # a cell with new-born mass and no slot sets the no-carrier bit; the kernel tests the
+        # cell's fixed-point mass, the oracle rho_b > 0, which differ only below 2^-40
+        nc = b["status"] & dogm.ST_NOCARRIER
+        got_nc = g.status() & dogm.ST_NOCARRIER
+        tiny = bool(((rho_b > 0) & (rho_b < 2.0 ** -40)).any())
+        if k != self.k_seen + 1 or tiny:
+            self.nocarrier = None
+        self.k_seen = k
+        if nc and not tiny:
+            assert got_nc, "no-carrier status bit not set"
+        if self.nocarrier is not None:
+            self.nocarrier |= nc
+            assert got_nc == self.nocarrier, "no-carrier status bit"
         self.stats["update.status"] = g.status()
         return cu
 
