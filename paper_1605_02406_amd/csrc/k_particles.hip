@@ -199,15 +199,29 @@ __global__ __launch_bounds__(kCellThreads) void k_born_offsets(Batch b)
     if (Stot != 0) o = (c == G.C) ? G.nb : slot_offset(E, Stot, G.nb);
     G.born_off[c] = o;
     bool no_carrier = false;
+    // new-born tiles [t_lo, t_hi) start inside this cell's slots [o, o1)
+    uint32_t t_lo = 0, t_hi = 0;
     if (c < G.C && Stot != 0 && G.nb > 0 && q != 0) {
         const uint32_t o1 = (c + 1 == G.C) ? G.nb : slot_offset(E + q, Stot, G.nb);
         if (o1 > o) {
             G.born_mark[o] = c;
-            for (uint32_t t = ceil_div_dev(o, kBornTile); t * (uint32_t)kBornTile < o1; ++t)
-                G.tile_first[t] = c;
+            t_lo = ceil_div_dev(o, kBornTile);
+            t_hi = ceil_div_dev(o1, kBornTile);
         } else {
             no_carrier = true;
         }
+    }
+    // A cell may hold all nb slots (nb / kBornTile tiles): a lane fills a short run of tiles
+    // itself and hands a long one to the whole wave.
+    constexpr uint32_t kLaneTiles = 4;
+    const bool wide = t_hi - t_lo > kLaneTiles;
+    if (!wide)
+        for (uint32_t t = t_lo; t < t_hi; ++t) G.tile_first[t] = c;
+    for (uint64_t wl = __ballot(wide); wl != 0; wl &= wl - 1) {
+        const int l = __ffsll((unsigned long long)wl) - 1;
+        const uint32_t lo = __shfl(t_lo, l, kWave), hi = __shfl(t_hi, l, kWave);
+        const uint32_t cl = __shfl(c, l, kWave);
+        for (uint32_t t = lo + (uint32_t)lane_id(); t < hi; t += kWave) G.tile_first[t] = cl;
     }
     // With births in every cell most waves may hold a cell without a slot.  Device-scope atomics
     // on one word serialise across the whole chip (about 12 ns each), so such waves store the

@@ -113,6 +113,21 @@ def test_all_particles_in_one_cell_and_outside():
     assert int((u32(g.v["cell_end"]) > u32(g.v["cell_start"])).sum()) == 1
 
 
+def test_births_in_few_cells_span_many_tiles():
+    """Births in three cells only (two of them in one wave of cells): each cell's slots span many
+    new-born tiles, whose first-cell entries the wave writes together."""
+    g, p = _fresh(32, 32, 20000, 6000, seed=4)
+    C = p.nx * p.ny
+    g.load_state(scenes.random_particles(p.nx, p.ny, 0.2, p.n_pers, 8))
+    pc = PerCall(g)
+    m = dict(m_occ=np.zeros(C), m_free=np.zeros(C))
+    m["m_occ"][[3, 10, 700]] = 0.9
+    pc.cycle(device_meas(m))
+    off = u32(g.v["born_off"]).astype(np.int64)
+    slots = off[1:] - off[:-1]
+    assert int((slots > 0).sum()) == 3 and int(slots.max()) > 6 * 256  # more than 4 tiles
+
+
 def test_vacuous_measurement_and_zero_weight():
     """Cycle 1 from the initial state (all weights 0) with an empty measurement: no mass,
     no births, the sorted state is kept by the resampling."""
