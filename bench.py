@@ -80,13 +80,14 @@ def algorithmic_bytes(kernel: str, nu: int, nb: int, C: int) -> float:
     sums per cell (64 B); the cell pass reads ranges, sums, m_F and the measurement (68 B) and
     writes masses, normalisers and moments (61 B) per cell; the slot offsets read rho_b and
     write o_c (8 B per cell); the tile pass rescales the persistent weights (key and weight
-    read, weight written: 12 B per particle) and writes each new-born slot's 25-byte record."""
+    read, weight written: 12 B per particle) and writes each new-born slot's 25-byte record.
+    The sort counts as one ideal pass over the 24-byte record (read and written once: 48 B per
+    particle and cycle), shared evenly by its scatter launches."""
     bits = sort_plan(C)
     if kernel == "k_predict":
         return 44.0 * nu
     if kernel == "k_sort_scatter":
-        per = [(24 if q == 0 else 28) + 28 for q in range(len(bits))]
-        return nu * sum(per) / len(per)
+        return 48.0 * nu / len(bits)
     if kernel == "k_sort_hist":
         return 4.0 * nu
     if kernel == "k_scan_rows":

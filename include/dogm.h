@@ -59,7 +59,7 @@ enum {
 
 /* Filter parameters (Table I and the process model of eq. (process)). */
 typedef struct dogm_params {
-    int32_t nx, ny;        /* cells along x and y, 1 <= nx, ny; nx*ny < 2^26               */
+    int32_t nx, ny;        /* cells along x and y, 1 <= nx, ny; nx*ny < 2^24 (see below)   */
     float cell_size;       /* cell edge r [m], > 0                                          */
     float dt;              /* time step T [s]                                               */
     float p_s;             /* persistence probability p_S, eq. (particle_persistence)       */
@@ -68,12 +68,18 @@ typedef struct dogm_params {
     float sigma_vel;       /* process-noise SD on velocity per step [m/s]                   */
     float sigma_birth_vel; /* SD of new-born velocity sigma_B,v [m/s] (Table I)             */
     float alpha_free;      /* free-mass discount alpha(T) in [0,1], eq. (DS_freespace_pred) */
-    int64_t n_pers;        /* persistent particles nu, 1 <= nu < 2^28                       */
+    int64_t n_pers;        /* persistent particles nu, 1 <= nu < 2^27 (see below)           */
     int64_t n_born;        /* new-born slots nu_b, 0 <= nu_b < 2^30                         */
     uint64_t seed;         /* Philox4x32-10 key                                            */
     uint32_t grid_id;      /* fourth Philox counter word: separates grids with one seed     */
     uint32_t model;        /* DOGM_MODEL_DS (0) or DOGM_MODEL_PHD_MIB (1), see below        */
 } dogm_params;
+
+/* Size limits.  Masses are summed in 64-bit fixed point (units of 2^-40; every cell holds at
+ * most mass 1), which cannot overflow for nx*ny < 2^24.  The systematic draws of Alg. 7 are
+ * evaluated in FP64 (spacing W/nu rounded once, then (j + U) times it); for nu < 2^27 the
+ * last draw stays below the joint weight W however large W is, so every draw finds a
+ * particle.  dogm_arena_bytes and dogm_init_grid return DOGM_EINVAL beyond either limit. */
 
 /* The per-cell step of the filter.
  *  DOGM_MODEL_DS: the Dempster-Shafer approximation of Sec. VI (eqs. (DS_particle_sum_pred) to

@@ -396,8 +396,10 @@ void or_persistent_update(int64_t C, double* w_sorted, const double* vx, const d
 uint64_t or_fixed40(double m) { return (uint64_t)floor(m * 0x1p40 + 0.5); }
 
 /* Slot allocation proportional to rho_b: exact prefix E_c of the fixed-point masses,
- * o_c = floor(nu_b * E_c / S) evaluated in FP64, o_C = nu_b.  S == 0 gives no births
- * (all offsets 0).  Returns S. */
+ * o_c = floor(nu_b * E_c / S) evaluated in FP64, o_C = nu_b.  Where E_c = S (every cell
+ * with new-born mass lies before c) the share is nu_b exactly, as the definition gives it;
+ * the FP64 evaluation alone can land one below.  S == 0 gives no births (all offsets 0).
+ * Returns S. */
 uint64_t or_born_alloc(int64_t C, int64_t nb, const double* rho_b, uint32_t* off)
 {
     uint64_t S = 0;
@@ -409,7 +411,7 @@ uint64_t or_born_alloc(int64_t C, int64_t nb, const double* rho_b, uint32_t* off
     uint64_t E = 0;
     for (int64_t c = 0; c < C; ++c) {
         double o = floor((double)E * (double)nb / (double)S);
-        if (o > (double)nb) o = (double)nb;
+        if (o > (double)nb || E >= S) o = (double)nb;
         off[c] = (uint32_t)o;
         E += or_fixed40(rho_b[c]);
     }
@@ -581,30 +583,6 @@ void or_resample_indices(int64_t nu, int64_t nb, const double* w_pers, const dou
 double or_resample_weight(uint64_t W_fixed, int64_t nu)
 {
     return (double)W_fixed * 0x1p-40 / (double)nu;
-}
-
-/* Gather of Alg. 7: the resampled state from the chosen indices. */
-void or_resample_gather(int64_t nu, const int64_t* idx, const double* px, const double* py,
-                        const double* pvx, const double* pvy, const double* bx, const double* by,
-                        const double* bvx, const double* bvy, double out_w, int keep_weights,
-                        const double* pw, double* ox, double* oy, double* ovx, double* ovy,
-                        double* ow)
-{
-    for (int64_t j = 0; j < nu; ++j) {
-        int64_t i = idx[j];
-        if (i < nu) {
-            ox[j] = px[i];
-            oy[j] = py[i];
-            ovx[j] = pvx[i];
-            ovy[j] = pvy[i];
-        } else {
-            ox[j] = bx[i - nu];
-            oy[j] = by[i - nu];
-            ovx[j] = bvx[i - nu];
-            ovy[j] = bvy[i - nu];
-        }
-        ow[j] = keep_weights ? pw[j] : out_w;
-    }
 }
 
 /* ------------------------------------------------------------------------------------ */

@@ -44,7 +44,9 @@ bool valid_params(const dogm_params* p)
 {
     if (!p) return false;
     if (p->nx < 1 || p->ny < 1) return false;
-    if ((int64_t)p->nx * (int64_t)p->ny >= (int64_t(1) << 26)) return false;
+    // fixed-point sums of masses (2^-40 units, at most 1 per cell plus half a unit per
+    // particle) stay below 2^64 for fewer than 2^24 cells
+    if ((int64_t)p->nx * (int64_t)p->ny >= (int64_t(1) << 24)) return false;
     if (!(std::isfinite(p->cell_size) && p->cell_size > 0.0f)) return false;
     if (!finite_in(p->dt, 0.0f, 1e6f)) return false;
     if (!finite_in(p->p_s, 0.0f, 1.0f) || !finite_in(p->p_b, 0.0f, 1.0f)) return false;
@@ -52,7 +54,9 @@ bool valid_params(const dogm_params* p)
         !finite_in(p->sigma_birth_vel, 0.0f, 1e6f))
         return false;
     if (!finite_in(p->alpha_free, 0.0f, 1.0f)) return false;
-    if (p->n_pers < 1 || p->n_pers >= (int64_t(1) << 28)) return false;
+    // below 2^27 the last systematic draw stays below the joint weight W after the three
+    // FP64 roundings of W, W / nu and (j + U) W / nu, also where W exceeds 2^53
+    if (p->n_pers < 1 || p->n_pers >= (int64_t(1) << 27)) return false;
     if (p->n_born < 0 || p->n_born >= (int64_t(1) << 30)) return false;
     if (p->model != DOGM_MODEL_DS && p->model != DOGM_MODEL_PHD_MIB) return false;
     return true;

@@ -32,7 +32,7 @@ constexpr int kSortItems = 4;
 constexpr int kSortTile = kSortThreads * kSortItems;  // 4096
 constexpr int kSortBits = 11;
 constexpr int kSortBins = 1 << kSortBits;  // 2048
-constexpr int kMaxPasses = 3;              // keys < 2^27 (C < 2^26 plus the outside key)
+constexpr int kMaxPasses = 3;              // keys <= C < 2^24 (C is the outside key)
 constexpr int kScanRowThreads = 256;       // one block scans a few digit rows of the histogram
 constexpr int kHistTile = kSortTile;       // keys per digit-histogram tile
 constexpr int kHistThreads = 1024;         // histogram blocks: kHistTile / kHistThreads keys each

@@ -159,8 +159,12 @@ hipError_t launch_predict(const GridRef* g, int n, hipStream_t s)
 __device__ __forceinline__ uint32_t ceil_div_dev(uint32_t a, uint32_t b) { return (a + b - 1) / b; }
 
 // o_c = floor(nu_b E_c / S) in FP64 with every operation rounded separately (no contraction).
+// Where all the new-born mass lies before the cell (E_c = S) the share is exactly nu_b: the
+// rounded product fl(S nu_b) / S may fall just below it, which would leave the last slot
+// without a cell that holds mass.
 __device__ __forceinline__ uint32_t slot_offset(uint64_t E, uint64_t S, uint32_t nb)
 {
+    if (E >= S) return nb;
     const double t = __ddiv_rn(__dmul_rn((double)E, (double)nb), (double)S);
     const double o = floor(t);
     return o > (double)nb ? nb : (uint32_t)o;
@@ -194,10 +198,11 @@ __global__ __launch_bounds__(kCellThreads) void k_born_offsets(Batch b)
     const uint64_t q = fixed40(rb);
     uint64_t total;
     const uint64_t E = before + block_excl_scan(q, tmp, &total);
-    if (c > G.C) return;
+    // lanes past the last offset stay in the wave: the wave-wide tile fill below needs them
+    const bool valid = c <= G.C;
     uint32_t o = 0;
     if (Stot != 0) o = (c == G.C) ? G.nb : slot_offset(E, Stot, G.nb);
-    G.born_off[c] = o;
+    if (valid) G.born_off[c] = o;
     bool no_carrier = false;
     // new-born tiles [t_lo, t_hi) start inside this cell's slots [o, o1)
     uint32_t t_lo = 0, t_hi = 0;

@@ -3,8 +3,9 @@
 // The CDF is an exact integer prefix sum of the weights in 2^-40 fixed point, so it does not
 // depend on the summation order; the per-tile totals were accumulated by the kernels that wrote
 // the weights.  Draw j sits at u_j = (j + U) d with the spacing d = W / nu rounded once to FP64,
-// and selects the first particle i with F_i > floor(u_j); for nu < 2^28 the last draw stays
-// below W by more than the rounding of d and of the product, so every draw finds a particle.
+// and selects the first particle i with F_i > floor(u_j); for nu < 2^27 the last draw stays
+// below W by more than the roundings of W, d and the product (1 - U >= 2^-24, so the margin is
+// at least 2^-24 / nu of W against three half-ulps), so every draw finds a particle.
 // Source i receives the draws J(F_{i-1}) <= j < J(F_i) with J(F) = min{ j : floor(u_j) >= F }.
 // One kernel: each tile adds up the totals of the tiles before it and scans its own weights
 // with wave prefix sums.  The draws of a wave's sources form one contiguous range; the wave

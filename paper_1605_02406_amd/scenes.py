@@ -78,17 +78,42 @@ class Scene:
     clutter: np.ndarray | None = None  # static occupied cells, bool [ny, nx]
     dt: float = FILTER["dt"]
     seed: int = 0
+    # half-width of a square around the sensor (grid centre) that boxes never enter: they
+    # reflect off it as off the border, so no box can cover the sensor and blind every ray
+    keepout: float = 0.0
 
     @property
     def size(self):
         return self.nx * self.cell, self.ny * self.cell
 
+    def _reflect_off_sensor(self, b: Box):
+        """Push a box that overlaps the keep-out square back out along the axis it entered the
+        least, mirrored, with that velocity component pointing away from the sensor."""
+        if self.keepout <= 0.0:
+            return
+        W, H = self.size
+        sx, sy = W / 2, H / 2
+        px = b.w / 2 + self.keepout - abs(b.cx - sx)  # overlap along x
+        py = b.h / 2 + self.keepout - abs(b.cy - sy)
+        if px <= 0.0 or py <= 0.0:
+            return
+        if px <= py:
+            side = 1.0 if b.cx >= sx else -1.0
+            b.cx += side * 2.0 * px
+            b.vx = side * abs(b.vx)
+        else:
+            side = 1.0 if b.cy >= sy else -1.0
+            b.cy += side * 2.0 * py
+            b.vy = side * abs(b.vy)
+
     def advance(self):
-        """Move every box by one time step, reflecting at the grid border."""
+        """Move every box by one time step, reflecting off the keep-out square around the
+        sensor and at the grid border."""
         W, H = self.size
         for b in self.boxes:
             b.cx += b.vx * self.dt
             b.cy += b.vy * self.dt
+            self._reflect_off_sensor(b)
             if b.cx - b.w / 2 < 0:
                 b.cx, b.vx = b.w / 2 + (b.w / 2 - b.cx), abs(b.vx)
             if b.cx + b.w / 2 > W:
@@ -155,7 +180,7 @@ def make_scene(wl: dict, seed: int | None = None) -> Scene:
         vels = [tuple(rng.uniform(-10, 10, 2)) for _ in range(3)]
         boxes = _place_boxes(rng, nx, ny, cell, sizes, vels, keepout=1.0)
         walls = [(0.2 * W, f * H - 0.2, 0.8 * W, f * H + 0.2) for f in (0.2, 0.8)]
-        return Scene(nx, ny, cell, boxes, walls=walls, seed=seed)
+        return Scene(nx, ny, cell, boxes, walls=walls, seed=seed, keepout=1.0)
     # boxes with sides U[0.5, 5] m, speed U[0, 20] m/s, heading U[0, 2 pi), plus static
     # clutter cells.
     nb = wl["n_boxes"]
@@ -168,7 +193,7 @@ def make_scene(wl: dict, seed: int | None = None) -> Scene:
     clutter = rng.random((ny, nx)) < wl.get("clutter", 0.0)
     cy0, cx0 = ny // 2, nx // 2
     clutter[max(cy0 - 2, 0):cy0 + 2, max(cx0 - 2, 0):cx0 + 2] = False
-    return Scene(nx, ny, cell, boxes, clutter=clutter, seed=seed)
+    return Scene(nx, ny, cell, boxes, clutter=clutter, seed=seed, keepout=3.0)
 
 
 def raycast_observed(occ: np.ndarray) -> np.ndarray:

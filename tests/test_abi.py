@@ -58,7 +58,7 @@ def test_arena_bytes_and_validation(dl):
     assert n2 > 8 * n
     bad = [dict(nx=0), dict(cell_size=0.0), dict(cell_size=float("nan")), dict(p_s=1.5),
            dict(p_b=-0.1), dict(alpha_free=2.0), dict(n_pers=0), dict(n_born=-1),
-           dict(n_pers=2 ** 28), dict(sigma_pos=-1.0)]
+           dict(n_pers=2 ** 27), dict(sigma_pos=-1.0), dict(nx=4096, ny=4096)]
     for kw in bad:
         args = dict(nx=64, ny=64, cell_size=0.2, n_pers=32768, n_born=8192)
         args.update(kw)
@@ -66,6 +66,9 @@ def test_arena_bytes_and_validation(dl):
         with pytest.raises(dl.DogmError) as e:
             dl.arena_bytes(q)
         assert e.value.code == dl.DOGM_EINVAL
+    # the largest sizes the boundary accepts
+    assert dl.arena_bytes(dl.make_params(4096, 4095, 0.2, 16, 0)) > 0
+    assert dl.arena_bytes(dl.make_params(8, 8, 0.2, 2 ** 27 - 1, 0)) > 0
     q = dl.make_params(64, 64, 0.2, 10, 0)
     q.model = 2  # neither the Dempster-Shafer nor the particle PHD/MIB model
     with pytest.raises(dl.DogmError):

@@ -1,0 +1,102 @@
+"""GPU parity at edge cases of the new-born slot allocation and of the initial state, each
+compared with the oracle on the GPU's own inputs (see tests/parity.py for the tolerances)."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1605_02406_amd import dogm, scenes
+from tests.parity import POS_TOL, PerCall, device_meas, host, oracle_params, u32
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    dogm.lib()
+
+
+def _fresh(nx, ny, nu, nb, **kw):
+    p = dogm.make_params(nx, ny, 0.2, nu, nb, **kw)
+    return dogm.Grid(p), p
+
+
+@pytest.mark.parametrize("nx,ny,nu", [(64, 64, 32768), (90, 20, 20001), (512, 512, 1 << 21)])
+def test_init_grid_matches_oracle(nx, ny, nu):
+    """dogm_init_grid: particles uniform over the grid, velocity N(0, sigma_B^2), weight 0,
+    element by element against the oracle's initial state; m_F = 0, cycle 1, status 0."""
+    g, p = _fresh(nx, ny, nu, 100, seed=5, grid_id=2, **scenes.FILTER)
+    torch.cuda.synchronize()
+    ref = oracle.init_state(oracle_params(p), nu)
+    got = g.state()
+    for c in ("x", "y", "vx", "vy"):
+        d = np.abs(got[c].astype(np.float64) - ref[c]) / np.maximum(np.abs(ref[c]), 1.0)
+        assert float(d.max()) <= POS_TOL, c
+    assert np.all(got["w"] == 0)
+    assert np.all(host(g.v["m_F"]) == 0)
+    assert int(g.v["cycle"].item()) == 1 and g.status() == 0
+
+
+def test_births_in_a_last_cell_of_a_ragged_grid():
+    """C = 10000 (not a multiple of 64) and every new-born slot in cell 9990, whose lane sits in
+    the last, partly filled wave of cells: the wave-wide fill of the new-born tiles' first
+    cells must cover all 40 tiles."""
+    g, p = _fresh(100, 100, 20000, 10000, seed=2, **scenes.FILTER)
+    C = p.nx * p.ny
+    pc = PerCall(g)
+    mo, mf = scenes.mass_levels()
+    for k in range(2):
+        m = dict(m_occ=np.zeros(C), m_free=np.full(C, mf))
+        m["m_occ"][9990], m["m_free"][9990] = mo, 0.0
+        pc.cycle(device_meas(m))
+        off = u32(g.v["born_off"]).astype(np.int64)
+        assert off[9990] == 0 and off[9991] == p.n_born
+        assert np.all(u32(g.v["bkey"]) == 9990)
+
+
+def test_slot_offsets_with_trailing_cells_without_births():
+    """nu_b = 777 with births only in the first cells: wherever the total S makes the FP64
+    quotient fl(fl(S nu_b) / S) fall below 777, the trailing cells must still start at slot 777
+    and the last slot must stay with the last cell that holds new-born mass.  Cycles run until
+    a few such totals have been met; every call is compared with the oracle."""
+    g, p = _fresh(32, 32, 6000, 777, seed=3, **scenes.FILTER)
+    C = p.nx * p.ny
+    pc = PerCall(g)
+    rng = np.random.default_rng(5)
+    mo, mf = scenes.mass_levels()
+    hits = 0
+    for k in range(150):
+        m = dict(m_occ=np.zeros(C), m_free=np.full(C, mf))
+        det = rng.random(700) < 0.3
+        m["m_occ"][:700][det] = mo
+        m["m_free"][:700][det] = 0.0
+        pc.cycle(device_meas(m))
+        S = int(g.v["S_fixed"].item())
+        if S and math.floor((float(S) * 777) / float(S)) < 777:
+            hits += 1
+            off = u32(g.v["born_off"]).astype(np.int64)
+            assert np.all(off[700:] == 777)
+            assert np.all(u32(g.v["bkey"]) < 700)
+            if hits == 3:
+                break
+    print("rounding-sensitive totals met:", hits, "in", k + 1, "cycles")
+    assert hits >= 1
+
+
+def test_blind_sensor_all_births_in_one_cell():
+    """Only the sensor's own cell is observed, with a detection: every new-born slot (64 tiles)
+    goes to that one cell, cycle after cycle."""
+    g, p = _fresh(128, 128, 1 << 17, 1 << 14, seed=6, **scenes.FILTER)
+    C = p.nx * p.ny
+    centre = 64 * 128 + 64
+    pc = PerCall(g)
+    mo, _ = scenes.mass_levels()
+    for k in range(3):
+        m = dict(m_occ=np.zeros(C), m_free=np.zeros(C))
+        m["m_occ"][centre] = mo
+        pc.cycle(device_meas(m))
+        assert np.all(u32(g.v["bkey"]) == centre)

@@ -19,14 +19,14 @@ def need_gpu():
 
 
 def test_largest_particle_count():
-    """nu = 2^28 - 1 (the largest the boundary accepts) on the 1024x1024 grid at 0.1 m with 2^20
+    """nu = 2^27 - 1 (the largest the boundary accepts) on the 1024x1024 grid at 0.1 m with 2^20
     new-born slots, second cycle: prediction parity on the first 2^20 particles (the oracle's
     random streams are per particle index), and on all particles the properties every correct
     result has: a stable sort (a permutation with non-decreasing keys whose cell ranges count
     the keys), per-cell sums of the sorted weights, the updated persistent mass of each cell
     equal to rho_p, and uniform weights W / nu after the resampling."""
     nx = ny = 1024
-    nu, nb, n_chk = (1 << 28) - 1, 1 << 20, 1 << 20
+    nu, nb, n_chk = (1 << 27) - 1, 1 << 20, 1 << 20
     C = nx * ny
     p = dogm.make_params(nx, ny, 0.1, nu, nb, seed=3, **scenes.FILTER)
     g = dogm.Grid(p)

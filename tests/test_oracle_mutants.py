@@ -32,6 +32,15 @@ MUTANTS = {
     "assoc_weight_missing_pA": ("pa * rho_b[c] / (double)na", "rho_b[c] / (double)na"),
     "born_alloc_inclusive_scan": ("double o = floor((double)E * (double)nb / (double)S);",
                                   "double o = floor((double)(E + or_fixed40(rho_b[c])) * (double)nb / (double)S);"),
+    "born_alloc_trailing_share_rounded": ("if (o > (double)nb || E >= S) o = (double)nb;",
+                                          "if (o > (double)nb) o = (double)nb;"),
+    "init_velocity_uses_process_noise": ("vx[i] = p->sigma_birth_vel * n0;",
+                                         "vx[i] = p->sigma_vel * n0;"),
+    "init_x_spans_ny": ("x[i] = or_uniform(b[0]) * (double)p->nx * p->cell_size;",
+                        "x[i] = or_uniform(b[0]) * (double)p->ny * p->cell_size;"),
+    "init_vy_repeats_vx_normal": ("vy[i] = p->sigma_birth_vel * n1;",
+                                  "vy[i] = p->sigma_birth_vel * n0;"),
+    "init_weight_uniform": ("        w[i] = 0.0;\n    }\n}", "        w[i] = 1.0 / (double)n;\n    }\n}"),
     "moments_mean_y_from_x": ("double mx = sx / r, my = sy / r;", "double mx = sx / r, my = sx / r;"),
     "variance_sign": ("var_x[c] = sxx / r - mx * mx;", "var_x[c] = sxx / r + mx * mx;"),
     "resample_off_by_one": ("while (i < N && F[i] <= t) ++i;", "while (i < N && F[i] < t) ++i;"),

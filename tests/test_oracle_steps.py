@@ -299,6 +299,35 @@ def test_born_alloc_proportional(orc):
     assert S == 0 and np.all(off == 0)
 
 
+def test_born_alloc_every_slot_lies_in_a_cell_with_mass(orc):
+    """Cells after the last cell with new-born mass own no slot, and every slot belongs to a cell
+    with mass (eq. (weights_unassociated) needs rho_b > 0 wherever n_c > 0).  With nu_b = 777 and
+    S = 248694042651024 (units of 2^-40) the FP64 quotient fl(fl(S nu_b) / S) is just below 777,
+    so the share of a trailing cell must come from its definition (all mass before it), not
+    from that rounding."""
+    rng = np.random.default_rng(9)
+    cases = [(777, 248694042651024)]
+    cases += [(int(rng.integers(2, 5000)), int(rng.integers(1 << 41, 1 << 47))) for _ in range(60)]
+    for nb, S in cases:
+        n_mass = 2 * -(-S // (1 << 40)) + 5  # cells holding S with masses of about 1/2
+        # n_mass near-equal parts of S, each moved by a random amount
+        base = np.full(n_mass, S // n_mass, np.int64)
+        base[: S - int(base.sum())] += 1
+        jig = rng.integers(0, (S // n_mass) // 4, n_mass // 2)
+        base[: n_mass // 2] -= jig
+        base[n_mass // 2: 2 * (n_mass // 2)] += jig
+        q = base
+        assert q.sum() == S and q.max() < (1 << 40)
+        C = n_mass + 30
+        rho_b = np.zeros(C)
+        rho_b[:n_mass] = q.astype(np.float64) * 2.0 ** -40  # exact: q < 2^40
+        off, S_got = orc.born_alloc(C, nb, rho_b)
+        assert S_got == S
+        assert np.all(off[n_mass:] == nb), (nb, S)
+        cell_of_slot = np.searchsorted(off, np.arange(nb), side="right") - 1
+        assert np.all(rho_b[cell_of_slot] > 0), (nb, S)
+
+
 def test_born_init_properties(orc):
     p = params(orc, nx=12, ny=9, nb=6000, seed=21)
     C = p.C
@@ -468,3 +497,104 @@ def test_resample_draw_lies_in_chosen_interval(orc):
             u = (j + Fraction(U)) * W / nu
             lo = F[i - 1] if i > 0 else 0
             assert lo <= u < F[i], (trial, j, i)
+
+
+# ---------------------------------------------------------------------------------------
+# initial state (the paper leaves it open; reading: particles spread uniformly over the grid,
+# velocity from the birth pdf, weight 0, so that the first cycle is all birth)
+# ---------------------------------------------------------------------------------------
+
+def test_init_state_distribution(orc):
+    """Positions uniform over [0, nx r) x [0, ny r) (a wide, flat grid so that the two extents
+    differ), velocity components N(0, sigma_B^2) and independent, weights exactly 0: each
+    checked against its distribution within 5 standard errors."""
+    p = params(orc, nx=90, ny=20, nu=60000, sigma_birth_vel=4.0, sigma_vel=0.5, seed=11)
+    n = p.n_pers
+    st = orc.init_state(p, n)
+    r = float(np.float32(p.cell_size))
+    ext = {"x": p.nx * r, "y": p.ny * r}
+    for c in ("x", "y"):
+        v = st[c] / ext[c]  # U(0, 1)
+        assert np.all((v > 0) & (v < 1)), c
+        assert abs(v.mean() - 0.5) < 5 * math.sqrt(1 / 12 / n), c
+        assert abs(v.var() - 1 / 12) < 5 * math.sqrt(1 / 180 / n), c
+        hist = np.bincount(np.minimum((v * 10).astype(int), 9), minlength=10)
+        assert np.all(np.abs(hist - n / 10) < 5 * math.sqrt(n * 0.09)), c  # flat in deciles
+    sB = float(np.float32(p.sigma_birth_vel))
+    for c in ("vx", "vy"):
+        z = st[c] / sB
+        assert abs(z.mean()) < 5 / math.sqrt(n), c
+        assert abs(z.var() - 1) < 5 * math.sqrt(2 / n), c
+        assert abs(np.mean(z ** 4) - 3) < 5 * math.sqrt(96 / n), c  # Gaussian kurtosis
+    corr = lambda a, b: np.corrcoef(a, b)[0, 1]  # noqa: E731
+    for a, b in (("vx", "vy"), ("x", "y"), ("x", "vx"), ("y", "vy")):
+        assert abs(corr(st[a], st[b])) < 5 / math.sqrt(n), (a, b)
+    assert np.all(st["w"] == 0.0)
+    # another seed or grid gives another state
+    q = params(orc, nx=90, ny=20, nu=1000, seed=12)
+    assert not np.array_equal(orc.init_state(q, 1000)["x"], st["x"][:1000])
+
+
+# ---------------------------------------------------------------------------------------
+# the exact fixed-point sums of the integer decisions against plain FP64 scans
+# ---------------------------------------------------------------------------------------
+
+def _c512_weights(orc, cycles=3):
+    """Persistent (sorted) and new-born weights and rho_b of the oracle's third cycle of the
+    512x512 / 2^21 + 2^18 workload."""
+    wl = scenes.WORKLOADS["c512"]
+    f = scenes.FILTER
+    p = orc.Params(wl["nx"], wl["ny"], wl["cell"], f["dt"], f["p_s"], f["p_b"], f["sigma_pos"],
+                   f["sigma_vel"], f["sigma_birth_vel"], f["alpha_free"], wl["n_pers"],
+                   wl["n_born"], seed=0, grid_id=0)
+    st = orc.init_state(p, p.n_pers)
+    m_F = np.zeros(p.C)
+    info = None
+    for k, m in enumerate(scenes.measurement_sequence(wl, cycles), start=1):
+        meas = {kk: np.asarray(v, np.float64) for kk, v in m.items()}
+        st, m_F, info = orc.cycle(p, k, st, m_F, meas)
+    return p, info
+
+
+def test_fixed_point_sums_against_plain_fp64_scans(orc):
+    """The integer decisions use sums of masses rounded to multiples of 2^-40 (exact in 64-bit
+    integers).  On the 512x512 workload's weights, a plain sequential FP64 scan (the textbook
+    CDF of Alg. 7 and the normalised born-mass scan of Alg. 5) picks the same resampling index
+    and the same slot offset except where the draw or the scaled prefix lies within the
+    difference of the two scans of a boundary; the counts are printed."""
+    p, info = _c512_weights(orc)
+    nu = p.n_pers
+    wj = np.concatenate([info["sorted"]["w"], info["born"]["w"]])
+    # resampling: fixed-point CDF (the oracle) vs a sequential FP64 CDF
+    U = orc.resample_offset(p, 3)
+    idx_fix, W_fix = orc.resample_indices(info["sorted"]["w"], info["born"]["w"], U)
+    F64 = np.cumsum(wj)  # sequential FP64 sums
+    W64 = F64[-1]
+    u64 = (np.arange(nu) + U) * (W64 / nu)
+    idx64 = np.minimum(np.searchsorted(F64, u64, side="right"), len(wj) - 1)
+    q = np.floor(wj * 2.0 ** 40 + 0.5)
+    Ffix = np.cumsum(q) * 2.0 ** -40  # exact integers times a power of two (below 2^53)
+    eps = float(np.max(np.abs(Ffix - F64))) + abs(W_fix * 2.0 ** -40 - W64) + 4 * W64 * 2.0 ** -52
+    diff = np.nonzero(idx_fix != idx64)[0]
+    for j in diff:
+        lo, hi = sorted((int(idx_fix[j]), int(idx64[j])))
+        gap = np.min(np.abs(F64[lo:hi] - u64[j]))  # boundaries between the two choices
+        assert gap <= eps, (j, gap, eps)
+    print(f"resampling: {len(diff)} of {nu} indices differ (CDF difference {eps:.2e} of "
+          f"W = {W64:.1f})")
+    # new-born slots: fixed-point prefix vs a sequential FP64 exclusive scan of rho_b
+    rho_b = info["rho_b"]
+    off_fix = info["born_off"]
+    E64 = np.concatenate([[0.0], np.cumsum(rho_b)])
+    S64 = E64[-1]
+    t64 = p.n_born * E64[:-1] / S64
+    off64 = np.minimum(np.floor(t64), p.n_born).astype(np.int64)
+    off64[E64[:-1] >= S64] = p.n_born
+    qb = np.floor(rho_b * 2.0 ** 40 + 0.5)
+    Efix = np.concatenate([[0.0], np.cumsum(qb)]) * 2.0 ** -40
+    eps_b = p.n_born * (float(np.max(np.abs(Efix - E64))) / S64 + 4 * 2.0 ** -52)
+    dc = np.nonzero(off_fix[:-1].astype(np.int64) != off64)[0]
+    for c in dc:
+        assert abs(t64[c] - round(t64[c])) <= eps_b, (c, t64[c], eps_b)
+    print(f"new-born slots: {len(dc)} of {p.C} offsets differ (band {eps_b:.2e} slots)")
+
