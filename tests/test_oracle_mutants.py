@@ -10,7 +10,8 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "dogm_oracle.c")
 PIN_SUITES = ["tests/test_oracle_rng.py", "tests/test_oracle_steps.py",
-              "tests/test_oracle_recursion.py", "tests/test_oracle_bayes.py"]
+              "tests/test_oracle_recursion.py", "tests/test_oracle_bayes.py",
+              "tests/test_oracle_exact_cycle.py"]
 
 MUTANTS = {
     "predict_uses_vy_for_x": ("p->dt * vx[i] + p->sigma_pos * nz[0]",
@@ -46,6 +47,10 @@ MUTANTS = {
     "resample_off_by_one": ("while (i < N && F[i] <= t) ++i;", "while (i < N && F[i] < t) ++i;"),
     "resample_weight_wrong_count": ("return (double)W_fixed * 0x1p-40 / (double)nu;",
                                     "return (double)W_fixed * 0x1p-40 / (double)(nu + 1);"),
+    "pignistic_half_dropped": ("pign[c] = o + 0.5 * (1.0 - o - f);", "pign[c] = o + (1.0 - o - f);"),
+    "born_x_from_row": ("bx[s] = ((double)ix + u0) * p->cell_size;",
+                        "bx[s] = ((double)iy + u0) * p->cell_size;"),
+    "covariance_mean_x_twice": ("cov_xy[c] = sxy / r - mx * my;", "cov_xy[c] = sxy / r - mx * mx;"),
     # the particle PHD/MIB cell step (Sec. V)
     "phd_births_dropped": ("const double rb = p->p_b * (1.0 - rp);", "const double rb = 0.0;"),
     "phd_detection_tp_fp_swapped": ("f = p_tp[c] / (p_fp[c] * (1.0 - r) + p_tp[c] * r);",
