@@ -58,33 +58,44 @@ def test_births_in_a_last_cell_of_a_ragged_grid():
         assert np.all(u32(g.v["bkey"]) == 9990)
 
 
+def _rounding_sensitive_masses(n_cells, nb, seed):
+    """FP32 masses for n_cells cells whose fixed-point total S (units of 2^-40) makes the FP64
+    quotient fl(fl(S nb) / S) fall below nb."""
+    # the product S nb must be inexact and lie low in its binade (below about 1.5 times its
+    # power of two) for its rounding error to reach half an ulp of the quotient: masses near
+    # 0.55 in 210 cells with nb = 777 put it near 1.36 * 2^56.  FP32 masses of 0.5 and more are
+    # multiples of 2^16 in fixed point, so a tenth of the cells get masses near 1e-6, whose
+    # fixed-point values have arbitrary low bits.  About one total in 32 qualifies.
+    rng = np.random.default_rng(seed)
+    for _ in range(2000):
+        v = rng.uniform(0.5, 0.6, n_cells).astype(np.float32)
+        v[::10] = rng.uniform(1e-6, 1e-5, v[::10].size).astype(np.float32)
+        # fixed point of each mass: nearest multiple of 2^-40, halves rounded up
+        S = int(sum(int(x) for x in np.floor(v.astype(np.float64) * 2.0 ** 40 + 0.5)))
+        if math.floor((float(S) * nb) / float(S)) < nb:
+            return v, S
+    raise AssertionError("no rounding-sensitive total found")
+
+
 def test_slot_offsets_with_trailing_cells_without_births():
-    """nu_b = 777 with births only in the first cells: wherever the total S makes the FP64
-    quotient fl(fl(S nu_b) / S) fall below 777, the trailing cells must still start at slot 777
-    and the last slot must stay with the last cell that holds new-born mass.  Cycles run until
-    a few such totals have been met; every call is compared with the oracle."""
-    g, p = _fresh(32, 32, 6000, 777, seed=3, **scenes.FILTER)
-    C = p.nx * p.ny
-    pc = PerCall(g)
-    rng = np.random.default_rng(5)
-    mo, mf = scenes.mass_levels()
-    hits = 0
-    for k in range(150):
-        m = dict(m_occ=np.zeros(C), m_free=np.full(C, mf))
-        det = rng.random(700) < 0.3
-        m["m_occ"][:700][det] = mo
-        m["m_free"][:700][det] = 0.0
-        pc.cycle(device_meas(m))
-        S = int(g.v["S_fixed"].item())
-        if S and math.floor((float(S) * 777) / float(S)) < 777:
-            hits += 1
-            off = u32(g.v["born_off"]).astype(np.int64)
-            assert np.all(off[700:] == 777)
-            assert np.all(u32(g.v["bkey"]) < 700)
-            if hits == 3:
-                break
-    print("rounding-sensitive totals met:", hits, "in", k + 1, "cycles")
-    assert hits >= 1
+    """nu_b = 777 with births only in cells below 700, and a new-born total S for which the
+    FP64 quotient fl(fl(S nu_b) / S) falls below 777: the trailing cells must still start at
+    slot 777 and the last slot must stay with the last cell that holds new-born mass.  In the
+    first cycle every weight is 0, so a detected cell's new-born mass is its m_occ exactly and
+    S is known in advance; three such totals, every call compared with the oracle."""
+    C = 32 * 32
+    for seed in range(3):
+        g, p = _fresh(32, 32, 6000, 777, seed=3 + seed, **scenes.FILTER)
+        cells = np.random.default_rng(10 + seed).choice(700, 210, replace=False)
+        v, S = _rounding_sensitive_masses(cells.size, 777, seed)
+        m = dict(m_occ=np.zeros(C), m_free=np.full(C, scenes.mass_levels()[1]))
+        m["m_occ"][cells] = v
+        m["m_free"][cells] = 0.0
+        PerCall(g).cycle(device_meas(m))
+        assert int(g.v["S_fixed"].item()) == S
+        off = u32(g.v["born_off"]).astype(np.int64)
+        assert np.all(off[cells.max() + 1:] == 777)
+        assert np.all(u32(g.v["bkey"]) <= cells.max())
 
 
 def test_blind_sensor_all_births_in_one_cell():
