@@ -222,6 +222,22 @@ int dogm_resample(dogm_grid* grid);
 /* predict, assign, update, moments, resample in order (one full cycle). */
 int dogm_step(dogm_grid* grid, const dogm_meas* meas);
 
+/* For callers that cannot allocate device memory or take an allocating code path (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation): the cycle of
+ * dogm_step, bit-identical to it, with the per-cycle scratch (digit histograms and their
+ * totals, partial sums of new-born masses and joint weights, first-slot marks, tile starts)
+ * and a private copy of the grid descriptor in a static device array of 16 MiB instead of the
+ * grid's arena.  The inputs and outputs stay the caller's: the grid's arena and `meas`.  The
+ * call allocates nothing (no hipMalloc or hipFree, no allocating library routine).  Each
+ * device holds one such array until the process ends, found at dogm_init_grid (or at the
+ * first call on a device) with that device current, and shared by every call on that device:
+ * calls that overlap in time on one device race and must be ordered by the caller (one
+ * stream, or events).  Nothing in the array needs clearing: every part is rewritten within
+ * the cycle before it is read.  DOGM_ESIZE, before anything is enqueued, if the grid's scratch
+ * exceeds the array (about 2 bytes per persistent particle plus 4 per new-born slot: e.g.
+ * nu = 2^22 with nu_b = 2^19 fits, nu = 2^23 does not); otherwise as dogm_step. */
+int dogm_step_noalloc(dogm_grid* grid, const dogm_meas* meas);
+
 /* One full cycle of n independent grids, each kernel launched once for all of them (grids of
  * different sizes share every launch).  All grids must have completed the same phase (ready
  * for predict); all work is enqueued on `stream`.  meas[i] belongs to grids[i].  The result of

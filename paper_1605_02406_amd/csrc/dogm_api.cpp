@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -79,6 +80,31 @@ T* at(char* base, size_t off)
     return reinterpret_cast<T*>(base + off);
 }
 
+// The per-cycle scratch of a grid: digit histograms of every sort tile (digit-major) with their
+// row totals, fixed-point partial sums of new-born masses and of joint weights, first-slot marks
+// and the first cell of every new-born tile.  Every array is rewritten within each cycle before
+// it is read, so none needs clearing.  Places the arrays at `base` (sizes and tilings of d must
+// be set; base may be null to only measure) and returns the bytes they take.
+size_t place_scratch(GridDev& d, char* base)
+{
+    Layout L;
+    const size_t o_hist = L.take(4ull * kSortBins * d.n_hist_tiles);
+    const size_t o_rowtot = L.take(4ull * kSortBins);
+    const size_t o_bpart = L.take(8ull * d.n_cell_parts);
+    const size_t o_mark = L.take(4ull * d.nb);
+    const size_t o_rpart = L.take(8ull * (d.n_res_ptiles + d.n_born_parts));
+    const size_t o_tfirst = L.take(4ull * d.n_born_parts);
+    if (base) {
+        d.hist = at<uint32_t>(base, o_hist);
+        d.rowtot = at<uint32_t>(base, o_rowtot);
+        d.bpart = at<uint64_t>(base, o_bpart);
+        d.rpart = at<uint64_t>(base, o_rpart);
+        d.born_mark = at<uint32_t>(base, o_mark);
+        d.tile_first = at<uint32_t>(base, o_tfirst);
+    }
+    return L.total;
+}
+
 // Builds the descriptor for `arena` (base may be null to only measure the size).
 GridDev describe(const dogm_params* p, char* base, size_t* bytes)
 {
@@ -146,12 +172,7 @@ GridDev describe(const dogm_params* p, char* base, size_t* bytes)
     size_t o_pf_nb[5];
     for (int i = 0; i < 5; ++i) o_pf_nb[i] = L.take(f_nb);
     const size_t o_bkey = L.take(f_nb), o_bas = L.take(nb);
-    const size_t o_hist = L.take(4ull * kSortBins * d.n_hist_tiles);
-    const size_t o_rowtot = L.take(4ull * kSortBins);
-    const size_t o_bpart = L.take(8ull * d.n_cell_parts);
-    const size_t o_mark = L.take(f_nb);
-    const size_t o_rpart = L.take(8ull * (d.n_res_ptiles + d.n_born_parts));
-    const size_t o_tfirst = L.take(4ull * d.n_born_parts);
+    const size_t o_scratch = L.take(place_scratch(d, nullptr));
     const size_t o_cyc = L.take(4), o_cycr = L.take(4), o_st = L.take(4), o_nc = L.take(4),
                  o_W = L.take(8), o_S = L.take(8);
     *bytes = L.total;
@@ -168,12 +189,7 @@ GridDev describe(const dogm_params* p, char* base, size_t* bytes)
     for (int i = 0; i < 5; ++i) *pf_nb[i] = at<float>(base, o_pf_nb[i]);
     d.bkey = at<uint32_t>(base, o_bkey);
     d.bassoc = at<uint8_t>(base, o_bas);
-    d.hist = at<uint32_t>(base, o_hist);
-    d.rowtot = at<uint32_t>(base, o_rowtot);
-    d.bpart = at<uint64_t>(base, o_bpart);
-    d.rpart = at<uint64_t>(base, o_rpart);
-    d.born_mark = at<uint32_t>(base, o_mark);
-    d.tile_first = at<uint32_t>(base, o_tfirst);
+    place_scratch(d, base + o_scratch);
     d.cycle = at<uint32_t>(base, o_cyc);
     d.cycle_run = at<uint32_t>(base, o_cycr);
     d.status = at<uint32_t>(base, o_st);
@@ -181,6 +197,37 @@ GridDev describe(const dogm_params* p, char* base, size_t* bytes)
     d.W_fixed = at<uint64_t>(base, o_W);
     d.S_fixed = at<uint64_t>(base, o_S);
     return d;
+}
+
+// The scratch of dogm_step_noalloc: one array per device, held until the process ends, with a
+// private copy of the stepped grid's descriptor at its start and that grid's per-cycle scratch
+// after it.  Host code uses only the device address hipGetSymbolAddress returns for it (the
+// array's name is a host-side stand-in), looked up once per device with that device current.
+constexpr size_t kStaticScratchBytes = size_t(16) << 20;
+constexpr size_t kStaticDescBytes = (sizeof(GridDev) + 255) & ~size_t(255);
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+std::mutex g_scratch_mu;
+std::vector<void*> g_scratch_ptr;  // per device id; null until looked up
+
+hipError_t static_scratch(void** out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if ((size_t)dev < g_scratch_ptr.size() && g_scratch_ptr[dev]) {
+        *out = g_scratch_ptr[dev];
+        return hipSuccess;
+    }
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!ptr) return hipErrorInvalidSymbol;
+    if ((size_t)dev >= g_scratch_ptr.size()) g_scratch_ptr.resize(dev + 1, nullptr);
+    g_scratch_ptr[dev] = ptr;
+    *out = ptr;
+    return hipSuccess;
 }
 
 // Velocity evidence (p_A > 0) is switched off: its kernels stay in the library but no entry
@@ -254,7 +301,11 @@ int dogm_init_grid(const dogm_params* params, void* arena, size_t arena_bytes,
     if ((reinterpret_cast<uintptr_t>(arena) & 255) != 0) return DOGM_EINVAL;
     size_t need = 0;
     describe(params, nullptr, &need);
-    if (arena_bytes < need) return DOGM_ESIZE;
+    if (arena_bytes < need) {
+        g_last_error = "dogm_init_grid: arena of " + std::to_string(arena_bytes) + " bytes, " +
+                       std::to_string(need) + " needed";
+        return DOGM_ESIZE;
+    }
     dogm_grid* g = new (std::nothrow) dogm_grid;
     if (!g) return DOGM_EINVAL;
     g->p = *params;
@@ -267,7 +318,10 @@ int dogm_init_grid(const dogm_params* params, void* arena, size_t arena_bytes,
     g->phase = kReady;
     g->assoc = false;
     std::memset(&g->last_meas, 0, sizeof(g->last_meas));
-    hipError_t e = launch_write_desc(g->hd, g->dd, g->stream);
+    // set-up of dogm_step_noalloc: the static scratch's address on the current device
+    void* scr = nullptr;
+    hipError_t e = static_scratch(&scr);
+    if (e == hipSuccess) e = launch_write_desc(g->hd, g->dd, g->stream);
     if (e == hipSuccess) {
         const GridRef r = g->ref();
         e = launch_init(&r, 1, g->stream);
@@ -437,6 +491,38 @@ int dogm_step(dogm_grid* grid, const dogm_meas* meas)
     return rc;
 }
 
+int dogm_step_noalloc(dogm_grid* grid, const dogm_meas* meas)
+{
+    if (!grid || !valid_meas(meas, grid->p.model)) return DOGM_EINVAL;
+    if (meas->p_assoc && !evidence_enabled()) return evidence_refused("dogm_step_noalloc");
+    if (grid->phase != kReady) return DOGM_ESTATE;
+    GridDev hs = grid->hd;
+    const size_t need = kStaticDescBytes + place_scratch(hs, nullptr);
+    if (need > kStaticScratchBytes) {
+        g_last_error = "dogm_step_noalloc: the grid's per-cycle scratch needs " +
+                       std::to_string(need) + " bytes, the static array holds " +
+                       std::to_string(kStaticScratchBytes);
+        return DOGM_ESIZE;
+    }
+    void* base = nullptr;
+    hipError_t e = static_scratch(&base);
+    if (e != hipSuccess) return hip_fail(e, "dogm_step_noalloc");
+    place_scratch(hs, static_cast<char*>(base) + kStaticDescBytes);
+    GridDev* dd = static_cast<GridDev*>(base);
+    const GridRef r{&hs, dd, to_dev(meas)};
+    const hipStream_t s = grid->stream;
+    e = launch_write_desc(hs, dd, s);
+    if (e == hipSuccess) e = launch_predict(&r, 1, s);
+    if (e == hipSuccess) e = launch_sort(&r, 1, s);
+    if (e == hipSuccess) e = launch_update(&r, 1, s);
+    if (e == hipSuccess) e = launch_moments(&r, 1, s);
+    if (e == hipSuccess) e = launch_resample(&r, 1, s);
+    if (e != hipSuccess) return hip_fail(e, "dogm_step_noalloc");
+    grid->assoc = false;
+    grid->cycle += 1;
+    return DOGM_OK;
+}
+
 int dogm_step_batch(dogm_grid* const* grids, const dogm_meas* meas, int n, dogm_stream_t stream)
 {
     if (n < 0 || (n > 0 && (!grids || !meas))) return DOGM_EINVAL;
@@ -474,7 +560,7 @@ const char* dogm_status_string(int code)
     switch (code) {
         case DOGM_OK: return "ok";
         case DOGM_EINVAL: return "invalid argument";
-        case DOGM_ESIZE: return "arena too small";
+        case DOGM_ESIZE: return g_last_error.empty() ? "buffer too small" : g_last_error.c_str();
         case DOGM_EHIP: return g_last_error.empty() ? "HIP error" : g_last_error.c_str();
         case DOGM_ESTATE: return "call out of order";
         case DOGM_ENOTIMPL: return g_last_error.empty() ? "not implemented" : g_last_error.c_str();

@@ -21,7 +21,8 @@ MODEL_DS, MODEL_PHD_MIB = 0, 1  # Sec. VI (Dempster-Shafer), Sec. V (particle PH
 # Names of the functions include/dogm.h declares.
 ABI = ["dogm_arena_bytes", "dogm_init_grid", "dogm_destroy", "dogm_set_stream", "dogm_set_cycle",
        "dogm_get_cycle", "dogm_view", "dogm_predict", "dogm_assign", "dogm_update",
-       "dogm_moments", "dogm_resample", "dogm_step", "dogm_step_batch", "dogm_status_string",
+       "dogm_moments", "dogm_resample", "dogm_step", "dogm_step_noalloc", "dogm_step_batch",
+       "dogm_status_string",
        "dogm_last_error", "dogm_trace_begin", "dogm_trace_end"]
 
 
@@ -93,6 +94,7 @@ def lib():
         L.dogm_view.argtypes = [vp, ct.POINTER(CViews)]
         L.dogm_update.argtypes = [vp, ct.POINTER(CMeas)]
         L.dogm_step.argtypes = [vp, ct.POINTER(CMeas)]
+        L.dogm_step_noalloc.argtypes = [vp, ct.POINTER(CMeas)]
         L.dogm_step_batch.argtypes = [ct.POINTER(vp), ct.POINTER(CMeas), i, vp]
         L.dogm_status_string.argtypes = [i]
         L.dogm_status_string.restype = ct.c_char_p
@@ -208,6 +210,12 @@ class Grid:
         self._sync_stream()
         self._keep = meas
         _check(lib().dogm_step(self.handle, ct.byref(meas.c)), "dogm_step")
+
+    def step_noalloc(self, meas: Meas):
+        """The cycle of step() with its per-cycle scratch in the library's static array."""
+        self._sync_stream()
+        self._keep = meas
+        _check(lib().dogm_step_noalloc(self.handle, ct.byref(meas.c)), "dogm_step_noalloc")
 
     def set_cycle(self, k: int):
         self._sync_stream()
