@@ -49,7 +49,7 @@ B_PER_CELL = 92
 CSRC = os.path.join(ROOT, "paper_1605_02406_amd", "csrc")
 KERNEL_SOURCE = {
     "k_predict": "k_particles.hip", "k_sort_hist": "k_sort.hip", "k_scan_rows": "k_sort.hip",
-    "k_sort_scatter": "k_sort.hip", "k_seg_sums<false>": "k_cells.hip",
+    "k_sort_scatter": "k_sort.hip", "k_gather": "k_sort.hip", "k_seg_sums<false>": "k_cells.hip",
     "k_seg_sums<true>": "k_cells.hip", "k_cells<false>": "k_cells.hip",
     "k_cells<true>": "k_cells.hip", "k_seg_moments": "k_cells.hip",
     "k_born_offsets": "k_particles.hip", "k_particle_tiles": "k_particles.hip",
@@ -72,8 +72,9 @@ def sort_plan(C: int, max_bits: int = 11):
 def algorithmic_bytes(kernel: str, nu: int, nb: int, C: int) -> float:
     """Algorithmic bytes of ONE launch of `kernel` on one grid (averaged over the launches of a
     cycle where they differ), from per-unit figures: predict reads x, y, vx, vy, w (20 B) and
-    writes them and the key (24 B); a sort pass reads the key, the source index (from the
-    second pass on) and the five state arrays and writes key, index and state (28 B); the
+    writes them and the key (24 B); a sort pass reads the key (and from the second pass on
+    the source index: 4 or 8 B) and writes key and index (8 B); the gather reads the
+    permutation and the predicted state (24 B) and writes the sorted state (20 B); the
     resampling reads every joint weight (4 B), the state of each chosen source (16 B) and
     writes the 20-byte state of every output; the per-cell pass of the assignment reads the
     sorted key, weight and velocity (16 B per particle) and writes the cell range and six FP64
@@ -81,13 +82,15 @@ def algorithmic_bytes(kernel: str, nu: int, nb: int, C: int) -> float:
     writes masses, normalisers and moments (61 B) per cell; the slot offsets read rho_b and
     write o_c (8 B per cell); the tile pass rescales the persistent weights (key and weight
     read, weight written: 12 B per particle) and writes each new-born slot's 25-byte record.
-    The sort counts as one ideal pass over the 24-byte record (read and written once: 48 B per
-    particle and cycle), shared evenly by its scatter launches."""
+    (The cycle budget B_alg instead counts the whole assignment as one ideal pass over the
+    24-byte record: 48 B per particle.)"""
     bits = sort_plan(C)
     if kernel == "k_predict":
         return 44.0 * nu
     if kernel == "k_sort_scatter":
-        return 48.0 * nu / len(bits)
+        return nu * sum((4.0 if q == 0 else 8.0) + 8.0 for q in range(len(bits))) / len(bits)
+    if kernel == "k_gather":
+        return 44.0 * nu
     if kernel == "k_sort_hist":
         return 4.0 * nu
     if kernel == "k_scan_rows":

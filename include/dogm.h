@@ -245,6 +245,34 @@ int dogm_step_noalloc(dogm_grid* grid, const dogm_meas* meas);
 int dogm_step_batch(dogm_grid* const* grids, const dogm_meas* meas, int n,
                     dogm_stream_t stream);
 
+/* The synthetic sensor ahead of the recursion.  The filter takes one measurement grid per
+ * cycle as its input (Sec. VII); these two calls generate it on the device from a scene, so a
+ * closed loop of scene, sensor and filter needs no host work per cycle.  Both only enqueue on
+ * `stream`; every pointer is device memory owned by the caller; cells are row-major.
+ *
+ * dogm_sensor_truth: occ[c] = 1 where the centre ((ix + 1/2) r, (iy + 1/2) r) of cell c lies in
+ * one of the n_rects axis-aligned rectangles rects[4i .. 4i+3] = (x0, y0, x1, y1) (bounds
+ * included; boxes and walls) or where static_occ[c] != 0 (optional, e.g. clutter), else 0.
+ * DOGM_EINVAL for a bad size, a NULL occ or rects with n_rects > 0, or cell_size <= 0. */
+int dogm_sensor_truth(const double* rects, int32_t n_rects, const uint8_t* static_occ,
+                      int32_t nx, int32_t ny, double cell_size, uint8_t* occ,
+                      dogm_stream_t stream);
+
+/* dogm_sensor_scan: the cells a sensor at the grid centre (nx/2, ny/2 in cell units) observes,
+ * and the evidence masses of one cycle.  One Amanatides-Woo traversal (FP64) per perimeter
+ * cell towards that cell's centre marks seen[c] = 1 in every cell it passes up to and
+ * including the first cell with occ != 0 (or the perimeter cell); every other cell gets 0.  In
+ * each observed cell one Bernoulli draw (Philox4x32-10, key `seed`, counter (c, cycle, 4, 0),
+ * uniform as in the filter) detects with probability p_d if occupied and p_cl if free; a
+ * detection gives (m_occ, m_free) = (2 P - 1, 0) with P = p_d / (p_d + p_cl), an observed cell
+ * without one (0, 1 - 2 Q) with Q = (1 - p_d) / ((1 - p_d) + (1 - p_cl)) (the masses whose
+ * pignistic transform is the Bayesian occupancy with prior 1/2), an unobserved cell (0, 0).
+ * m_occ and m_free may both be NULL (ray cast only).  DOGM_EINVAL for a bad size or pointer,
+ * probabilities outside [0, 1] or p_d < p_cl (negative evidence). */
+int dogm_sensor_scan(const uint8_t* occ, int32_t nx, int32_t ny, double p_d, double p_cl,
+                     uint64_t seed, uint32_t cycle, uint8_t* seen, float* m_occ, float* m_free,
+                     dogm_stream_t stream);
+
 /* Per-kernel timing on the device clock.  While a trace is active, every launch of the kernel
  * named `kernel` (every kernel if NULL) that the calling thread enqueues through this library
  * is bracketed by two of the caller's HIP events (hipEvent_t, created with timing enabled),

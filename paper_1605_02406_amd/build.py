@@ -19,7 +19,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libdogm.so")
-SOURCES = ["k_particles.hip", "k_sort.hip", "k_cells.hip", "k_resample.hip", "dogm_api.cpp"]
+SOURCES = ["k_particles.hip", "k_sort.hip", "k_cells.hip", "k_resample.hip", "k_sensor.hip",
+           "dogm_api.cpp"]
 ARCH = "gfx950"
 
 

@@ -149,10 +149,9 @@ GridDev describe(const dogm_params* p, char* base, size_t* bytes)
     Layout L;
     L.take(sizeof(GridDev));
     const size_t f_nu = 4ull * nu, f_nb = 4ull * nb, f_c = 4ull * C, d_c = 8ull * C;
-    float** pf_nu[] = {&d.x, &d.y, &d.vx, &d.vy, &d.w, &d.sx, &d.sy, &d.svx, &d.svy, &d.sw,
-                       &d.tx, &d.ty, &d.tvx, &d.tvy, &d.tw};
-    size_t o_pf_nu[15];
-    for (int i = 0; i < 15; ++i) o_pf_nu[i] = L.take(f_nu);
+    float** pf_nu[] = {&d.x, &d.y, &d.vx, &d.vy, &d.w, &d.sx, &d.sy, &d.svx, &d.svy, &d.sw};
+    size_t o_pf_nu[10];
+    for (int i = 0; i < 10; ++i) o_pf_nu[i] = L.take(f_nu);
     uint32_t** pu_nu[] = {&d.key, &d.skey, &d.perm, &d.tkey, &d.tval};
     size_t o_pu_nu[5];
     for (int i = 0; i < 5; ++i) o_pu_nu[i] = L.take(f_nu);
@@ -178,7 +177,7 @@ GridDev describe(const dogm_params* p, char* base, size_t* bytes)
     *bytes = L.total;
     if (!base) return d;
 
-    for (int i = 0; i < 15; ++i) *pf_nu[i] = at<float>(base, o_pf_nu[i]);
+    for (int i = 0; i < 10; ++i) *pf_nu[i] = at<float>(base, o_pf_nu[i]);
     for (int i = 0; i < 5; ++i) *pu_nu[i] = at<uint32_t>(base, o_pu_nu[i]);
     for (int i = 0; i < 2; ++i) *pu_c[i] = at<uint32_t>(base, o_pu_c[i]);
     for (int i = 0; i < 4; ++i) *pd_c[i] = at<double>(base, o_pd_c[i]);
@@ -553,6 +552,36 @@ int dogm_step_batch(dogm_grid* const* grids, const dogm_meas* meas, int n, dogm_
     }
     for (int i = 0; i < n; ++i) grids[i]->cycle += 1;
     return DOGM_OK;
+}
+
+int dogm_sensor_truth(const double* rects, int32_t n_rects, const uint8_t* static_occ,
+                      int32_t nx, int32_t ny, double cell_size, uint8_t* occ,
+                      dogm_stream_t stream)
+{
+    if (nx < 1 || ny < 1 || (int64_t)nx * (int64_t)ny >= (int64_t(1) << 24) || !occ) return DOGM_EINVAL;
+    if (n_rects < 0 || (n_rects > 0 && !rects)) return DOGM_EINVAL;
+    if (!(std::isfinite(cell_size) && cell_size > 0.0)) return DOGM_EINVAL;
+    const hipError_t e = launch_sensor_truth(rects, n_rects, static_occ, nx, ny, cell_size, occ,
+                                             nullptr, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? DOGM_OK : hip_fail(e, "dogm_sensor_truth");
+}
+
+int dogm_sensor_scan(const uint8_t* occ, int32_t nx, int32_t ny, double p_d, double p_cl,
+                     uint64_t seed, uint32_t cycle, uint8_t* seen, float* m_occ, float* m_free,
+                     dogm_stream_t stream)
+{
+    if (nx < 1 || ny < 1 || (int64_t)nx * (int64_t)ny >= (int64_t(1) << 24)) return DOGM_EINVAL;
+    if (!occ || !seen || (!m_occ) != (!m_free)) return DOGM_EINVAL;
+    if (!(p_d >= 0.0 && p_d <= 1.0 && p_cl >= 0.0 && p_cl <= 1.0)) return DOGM_EINVAL;
+    // evidence masses whose pignistic transform is the Bayesian occupancy with prior 1/2
+    const double hit = p_d / (p_d + p_cl);
+    const double miss = (1.0 - p_d) / ((1.0 - p_d) + (1.0 - p_cl));
+    const double mo = 2.0 * hit - 1.0, mf = 1.0 - 2.0 * miss;
+    if (!(mo >= 0.0 && mo <= 1.0 && mf >= 0.0 && mf <= 1.0)) return DOGM_EINVAL;
+    const hipError_t e = launch_sensor_scan(occ, nx, ny, true, p_d, p_cl, (float)mo, (float)mf,
+                                            seed, cycle, seen, m_occ, m_free,
+                                            static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? DOGM_OK : hip_fail(e, "dogm_sensor_scan");
 }
 
 const char* dogm_status_string(int code)

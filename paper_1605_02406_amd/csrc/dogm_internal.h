@@ -125,8 +125,7 @@ struct GridT {
     // particles sorted by cell
     P<float> sx, sy, svx, svy, sw;
     P<uint32_t> skey, perm;
-    // ping-pong partner of the sorted arrays during the sort
-    P<float> tx, ty, tvx, tvy, tw;
+    // ping-pong partner of the sorted keys and the permutation during the sort
     P<uint32_t> tkey, tval;
     // cells
     P<uint32_t> cstart, cend;

@@ -1,11 +1,15 @@
-// Alg. 2, first line: stable sort of the particles by cell key.
+// Alg. 2, first line: stable sort of the particles by cell key, and the particle state in sorted
+// order.
 //
-// LSD radix sort over digits of at most kSortBits bits (two passes for grids up to 2^20 cells);
-// each pass moves the key, the source index and the FP32 particle state.  A pass is three
-// kernels that communicate only through memory: the digit histogram of every tile (for the
-// first pass it comes from the prediction kernel), a scan of each digit's row of tile counts,
-// and the scatter.  No block waits for another.  The per-cell pass that follows the sort marks
-// where each cell's run of sorted particles starts and ends.
+// LSD radix sort of (key, source index) pairs over digits of at most kSortBits bits (two passes
+// for grids up to 2^20 cells), then one gather of the predicted state into sorted order.  A pass
+// is three kernels that communicate only through memory: the digit histogram of every tile (for
+// the first pass it comes from the prediction kernel), a scan of each digit's row of tile counts,
+// and the scatter.  No block waits for another.  Only the 8-byte pairs travel through the
+// passes; the 20-byte state moves once, in the gather, whose reads follow the final order: after
+// resampling the particles are stored in cell order and one prediction moves them by a few
+// cells, so neighbouring sorted positions mostly read neighbouring sources.  The per-cell pass
+// that follows marks where each cell's run of sorted particles starts and ends.
 //
 // Stable ranking inside a tile: each of the block's 16 waves owns a contiguous sixteenth of the
 // tile (256 keys) and walks it 64 keys at a time; lanes holding the same digit find each other
@@ -22,19 +26,17 @@ namespace dogm {
 
 constexpr int kSortWaves = kSortThreads / kWave;
 
-// The arrays one pass reads and writes, as raw pointers (P = HostPtr) or global-space views.
+// The pairs one pass reads and writes, as raw pointers (P = HostPtr) or global-space views.
 template <template <typename> class P>
 struct SortArrays {
     P<uint32_t> ik;
     P<uint32_t> iv;  // null: the source index is the element index
-    P<float> ix, iy, ivx, ivy, iw;
     P<uint32_t> ok, ov;
-    P<float> ox, oy, ovx, ovy, ow;
 };
 
-// Pass p of P reads the predicted state (p == 0) or the previous pass's output and writes the
-// sorted arrays on the last pass; the passes alternate between the sorted and the temporary
-// arrays so that the last one lands in the sorted arrays.
+// Pass p of P reads the predicted keys (p == 0) or the previous pass's pairs and writes the sorted
+// keys and the permutation on the last pass; the passes alternate between those and the
+// temporary pairs so that the last one lands in the sorted arrays.
 template <template <typename> class P>
 __device__ __forceinline__ SortArrays<P> sort_arrays(const GridT<P>& G, uint32_t pass)
 {
@@ -42,20 +44,15 @@ __device__ __forceinline__ SortArrays<P> sort_arrays(const GridT<P>& G, uint32_t
     SortArrays<P> a;
     if (pass == 0) {
         a.ik = G.key; a.iv = P<uint32_t>{};
-        a.ix = G.x; a.iy = G.y; a.ivx = G.vx; a.ivy = G.vy; a.iw = G.w;
     } else if (dst_sorted) {
         a.ik = G.tkey; a.iv = G.tval;
-        a.ix = G.tx; a.iy = G.ty; a.ivx = G.tvx; a.ivy = G.tvy; a.iw = G.tw;
     } else {
         a.ik = G.skey; a.iv = G.perm;
-        a.ix = G.sx; a.iy = G.sy; a.ivx = G.svx; a.ivy = G.svy; a.iw = G.sw;
     }
     if (dst_sorted) {
         a.ok = G.skey; a.ov = G.perm;
-        a.ox = G.sx; a.oy = G.sy; a.ovx = G.svx; a.ovy = G.svy; a.ow = G.sw;
     } else {
         a.ok = G.tkey; a.ov = G.tval;
-        a.ox = G.tx; a.oy = G.ty; a.ovx = G.tvx; a.ovy = G.tvy; a.ow = G.tw;
     }
     return a;
 }
@@ -123,17 +120,6 @@ __global__ __launch_bounds__(kScanRowThreads) void k_scan_rows(Batch b, uint32_t
         carry += total;
     }
     if (threadIdx.x == 0) G.rowtot[d] = carry;
-}
-
-// Reads one state array for a wave's items (coalesced, zeros past the end).
-__device__ __forceinline__ void load_items(const float* in, uint32_t base, uint32_t n,
-                                           float (&out)[kSortItems])
-{
-#pragma unroll
-    for (int it = 0; it < kSortItems; ++it) {
-        const uint32_t idx = base + it * kWave + lane_id();
-        out[it] = idx < n ? in[idx] : 0.0f;
-    }
 }
 
 // Writes one payload array in destination order: every element goes to its local sorted slot in
@@ -207,9 +193,6 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(Batch b, uint32_t
         k[it] = valid ? A.ik[idx] : 0u;
         v[it] = valid ? (A.iv ? A.iv[idx] : idx) : 0u;
     }
-    // the first state array is read while the tile is ranked
-    float pa[kSortItems], pb[kSortItems];
-    load_items(A.ix, base, G.nu, pa);
     // stable ranks inside the wave's quarter
 #pragma unroll
     for (int it = 0; it < kSortItems; ++it) {
@@ -297,18 +280,50 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(Batch b, uint32_t
             }
         }
     }
-    // the source index and the state, one array at a time through the same LDS row; the next
-    // array's loads are in flight while the current one is staged
+    // the source index through the same LDS row
     move_out(v, A.ov, stage, lpos, gpos);
-    load_items(A.iy, base, G.nu, pb);
-    move_out(pa, A.ox, stage, lpos, gpos);
-    load_items(A.ivx, base, G.nu, pa);
-    move_out(pb, A.oy, stage, lpos, gpos);
-    load_items(A.ivy, base, G.nu, pb);
-    move_out(pa, A.ovx, stage, lpos, gpos);
-    load_items(A.iw, base, G.nu, pa);
-    move_out(pb, A.ovy, stage, lpos, gpos);
-    move_out(pa, A.ow, stage, lpos, gpos);
+}
+
+// The predicted state in sorted order: sorted position i takes particle perm[i].  Each thread
+// moves kGatherItems positions kGatherThreads apart, so a wave's reads of the permutation and its
+// writes are contiguous and its reads of the state follow the sources of 64 neighbouring sorted
+// positions.  Neighbouring tiles read neighbouring sources: each XCD walks one run of tiles.
+constexpr int kGatherThreads = 256;
+constexpr int kGatherItems = 4;
+constexpr int kGatherTile = kGatherThreads * kGatherItems;
+
+__global__ __launch_bounds__(kGatherThreads) void k_gather(Batch b)
+{
+    const int gi = batch_grid(b);
+    const GridView G = grid_view(b.g[gi]);
+    const uint32_t tile = xcd_tile(b, gi);
+    if (tile * kGatherTile >= G.nu) return;
+    uint32_t src[kGatherItems];
+#pragma unroll
+    for (int it = 0; it < kGatherItems; ++it) {
+        const uint32_t i = tile * kGatherTile + it * kGatherThreads + threadIdx.x;
+        src[it] = i < G.nu ? G.perm[i] : 0u;
+    }
+    float x[kGatherItems], y[kGatherItems], vx[kGatherItems], vy[kGatherItems], w[kGatherItems];
+#pragma unroll
+    for (int it = 0; it < kGatherItems; ++it) {
+        x[it] = G.x[src[it]];
+        y[it] = G.y[src[it]];
+        vx[it] = G.vx[src[it]];
+        vy[it] = G.vy[src[it]];
+        w[it] = G.w[src[it]];
+    }
+#pragma unroll
+    for (int it = 0; it < kGatherItems; ++it) {
+        const uint32_t i = tile * kGatherTile + it * kGatherThreads + threadIdx.x;
+        if (i < G.nu) {
+            G.sx[i] = x[it];
+            G.sy[i] = y[it];
+            G.svx[i] = vx[it];
+            G.svy[i] = vy[it];
+            G.sw[i] = w[it];
+        }
+    }
 }
 
 // The scatter's dynamic LDS (up to 96 KiB with 11-bit digits) is above the default limit: raise
@@ -362,6 +377,11 @@ hipError_t launch_sort(const GridRef* g, int n, hipStream_t s)
                            sizeof(uint32_t) * (2 * (size_t)nbins + kSortTile);
         if (tiles) DOGM_LAUNCH(k_sort_scatter, dim3(tiles), dim3(kSortThreads), lds, s, b, pass);
     }
+    Batch b;
+    const uint32_t gblocks = make_batch(b, g, n, [](const GridDev& G) {
+        return xcd_blocks(ceil_div(G.nu, kGatherTile));
+    });
+    if (gblocks) DOGM_LAUNCH(k_gather, dim3(gblocks), dim3(kGatherThreads), 0, s, b);
     // the particle range of every occupied cell, with the per-cell sums of the update
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? launch_cell_sums(g, n, s) : e;

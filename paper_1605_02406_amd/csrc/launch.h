@@ -88,5 +88,12 @@ hipError_t launch_born_offsets(const GridRef* g, int n, hipStream_t s);   // Alg
 hipError_t launch_particle_tiles(const GridRef* g, int n, hipStream_t s); // Alg. 4 + 5
 hipError_t launch_moments(const GridRef* g, int n, hipStream_t s);        // Alg. 6
 hipError_t launch_resample(const GridRef* g, int n, hipStream_t s);       // Alg. 7
+// the synthetic sensor ahead of the recursion
+hipError_t launch_sensor_truth(const double* rects, int n_rects, const uint8_t* static_occ,
+                               int nx, int ny, double cell, uint8_t* occ, uint8_t* seen,
+                               hipStream_t s);
+hipError_t launch_sensor_scan(const uint8_t* occ, int nx, int ny, bool clear, double p_d,
+                              double p_cl, float m_o, float m_f, uint64_t seed, uint32_t cycle,
+                              uint8_t* seen, float* m_occ, float* m_free, hipStream_t s);
 
 }  // namespace dogm

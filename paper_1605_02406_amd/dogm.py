@@ -23,7 +23,8 @@ ABI = ["dogm_arena_bytes", "dogm_init_grid", "dogm_destroy", "dogm_set_stream", 
        "dogm_get_cycle", "dogm_view", "dogm_predict", "dogm_assign", "dogm_update",
        "dogm_moments", "dogm_resample", "dogm_step", "dogm_step_noalloc", "dogm_step_batch",
        "dogm_status_string",
-       "dogm_last_error", "dogm_trace_begin", "dogm_trace_end"]
+       "dogm_last_error", "dogm_trace_begin", "dogm_trace_end", "dogm_sensor_truth",
+       "dogm_sensor_scan"]
 
 
 class DogmError(RuntimeError):
@@ -101,6 +102,10 @@ def lib():
         L.dogm_last_error.restype = ct.c_char_p
         L.dogm_trace_begin.argtypes = [ct.POINTER(vp), ct.POINTER(ct.c_char_p), i, ct.c_char_p]
         L.dogm_trace_end.argtypes = [ct.POINTER(i)]
+        L.dogm_sensor_truth.argtypes = [vp, ct.c_int32, vp, ct.c_int32, ct.c_int32, ct.c_double,
+                                        vp, vp]
+        L.dogm_sensor_scan.argtypes = [vp, ct.c_int32, ct.c_int32, ct.c_double, ct.c_double,
+                                       ct.c_uint64, ct.c_uint32, vp, vp, vp, vp]
         for name in ABI:
             if name not in ("dogm_status_string", "dogm_last_error"):
                 getattr(L, name).restype = i
@@ -292,3 +297,25 @@ def step_batch(grids: list, meas: list, stream=None):
         g._keep = m
     _check(lib().dogm_step_batch(hs, ms, n, ct.c_void_p(_stream_ptr(stream))),
            "dogm_step_batch")
+
+
+def _ptr(t):
+    return None if t is None else ct.c_void_p(t.data_ptr())
+
+
+def sensor_truth(rects, static_occ, nx: int, ny: int, cell: float, occ, stream=None):
+    """Truth grid on the device: rects float64 [n, 4] (x0, y0, x1, y1), static_occ uint8 [C] or
+    None, occ uint8 [C] (written)."""
+    n = 0 if rects is None else int(rects.shape[0])
+    _check(lib().dogm_sensor_truth(_ptr(rects), n, _ptr(static_occ), nx, ny, float(cell),
+                                   _ptr(occ), ct.c_void_p(_stream_ptr(stream))),
+           "dogm_sensor_truth")
+
+
+def sensor_scan(occ, nx: int, ny: int, p_d: float, p_cl: float, seed: int, cycle: int, seen,
+                m_occ=None, m_free=None, stream=None):
+    """Ray cast and evidence masses of one cycle on the device (seen uint8 [C], m_occ and
+    m_free float32 [C], all written)."""
+    _check(lib().dogm_sensor_scan(_ptr(occ), nx, ny, float(p_d), float(p_cl), seed, cycle,
+                                  _ptr(seen), _ptr(m_occ), _ptr(m_free),
+                                  ct.c_void_p(_stream_ptr(stream))), "dogm_sensor_scan")

@@ -123,6 +123,17 @@ class Scene:
             if b.cy + b.h / 2 > H:
                 b.cy, b.vy = H - b.h / 2 - (b.cy + b.h / 2 - H), -abs(b.vy)
 
+    def rects(self) -> np.ndarray:
+        """The walls and boxes as float64 rectangles [n, 4] (x0, y0, x1, y1)."""
+        r = list(self.walls) + [(b.cx - b.w / 2, b.cy - b.h / 2, b.cx + b.w / 2, b.cy + b.h / 2)
+                                for b in self.boxes]
+        return np.array(r, np.float64).reshape(-1, 4)
+
+    def static_mask(self) -> np.ndarray:
+        """Static occupied cells other than walls (bool [ny, nx])."""
+        return (np.zeros((self.ny, self.nx), bool) if self.clutter is None
+                else self.clutter.copy())
+
     def truth(self) -> np.ndarray:
         """Occupied cells (bool [ny, nx]): cell centre inside a box, a wall or clutter."""
         xc = (np.arange(self.nx) + 0.5) * self.cell
