@@ -140,10 +140,31 @@ def measured_traffic(kernel: str, workload: str, outdir: str = PROFILES):
     return rec.get("hbm_bytes_per_launch")
 
 
+def precision_study(path: str = os.path.join(PROFILES, "precision_c1024.json")):
+    """The committed record of the precision study on the 1024x1024 workload (maximum and 99th
+    percentile of each output's error against the oracle in both precision modes, and the
+    resampling indices that plain FP64 and FP32 CDFs would change), or None."""
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    keep = ("predict.x", "predict.vx", "update.m_O", "update.rho_b", "update.w", "born.x",
+            "moments.mean_x", "moments.var_x")
+    return {"workload": rec["workload"], "source": "profiles/precision_c1024.json",
+            "modes": {m["mode"]: {"errors": {k: v for k, v in m["errors"].items() if k in keep},
+                                  "resample_cdf_variants": {
+                                      k: v["indices_differing"]
+                                      for k, v in m["resample_cdf_variants"].items() if k != "W"}}
+                      for m in rec["modes"]}}
+
+
 def short_name(full: str) -> str:
     """Kernel name as the trace hook reports it, from the demangled name in a counter file."""
     name = full.split("(")[0].replace("void ", "").replace("dogm::", "").strip()
-    return name
+    # the precision mode's template argument is not part of the traced name
+    for t in ("<float>", "<double>"):
+        name = name.replace(t, "")
+    return name.replace(", float>", ">").replace(", double>", ">")
 
 
 def write_traffic(fetch_csv: str, write_csv: str, workload: str, commands, outdir: str = PROFILES):
@@ -213,6 +234,8 @@ def parse():
     ap.add_argument("--workload", default="c512")
     ap.add_argument("--model", choices=("ds", "phd"), default="ds",
                     help="per-cell step: Dempster-Shafer (Sec. VI) or particle PHD/MIB (Sec. V)")
+    ap.add_argument("--precision", choices=("fp32", "fp64"), default="fp32",
+                    help="FP32 state with exact integer decisions (default) or all-FP64")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="host time budget of the oracle's CPU baseline: whole cycles are run "
                          "until it is spent (0: skip)")
@@ -254,6 +277,8 @@ def main():
     p = dogm.make_params(wl["nx"], wl["ny"], wl["cell"], wl["n_pers"], wl["n_born"],
                          seed=wl.get("seed", 0),
                          model=dogm.MODEL_PHD_MIB if args.model == "phd" else dogm.MODEL_DS,
+                         precision=(dogm.PRECISION_FP64 if args.precision == "fp64"
+                                    else dogm.PRECISION_FP32),
                          **scenes.FILTER)
     C = wl["nx"] * wl["ny"]
     nu, nb = wl["n_pers"], wl["n_born"]
@@ -365,10 +390,11 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f64" if args.precision == "fp64" else "f32",
         "data": "synthetic",
         "config": {"workload": describe_workload(wl) + (
-                       "; particle PHD/MIB model (Sec. V)" if args.model == "phd" else ""),
+                       "; particle PHD/MIB model (Sec. V)" if args.model == "phd" else "") + (
+                       "; all-FP64 precision mode" if args.precision == "fp64" else ""),
                    "nx": wl["nx"], "ny": wl["ny"], "cell_m": wl["cell"], "n_pers": nu,
                    "n_born": nb},
         "particles_per_s": cycles_per_s * nu,
@@ -397,6 +423,10 @@ def main():
         "sort": {"keys_per_s": nu / (per_call["assign"] * 1e-3),
                  "ideal_pass_keys_per_s": HBM_PEAK_GBS * 1e9 / 48.0},
     }
+
+    study = precision_study()
+    if study is not None:
+        out["precision_study"] = study
 
     modes = {}
     if args.batch_steps > 0:

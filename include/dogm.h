@@ -73,7 +73,17 @@ typedef struct dogm_params {
     uint64_t seed;         /* Philox4x32-10 key                                            */
     uint32_t grid_id;      /* fourth Philox counter word: separates grids with one seed     */
     uint32_t model;        /* DOGM_MODEL_DS (0) or DOGM_MODEL_PHD_MIB (1), see below        */
+    uint32_t precision;    /* DOGM_PRECISION_FP32 (0) or DOGM_PRECISION_FP64 (1), see below */
 } dogm_params;
+
+/* Precision modes.  DOGM_PRECISION_FP32: the particle state and the per-cell masses and moments
+ * are stored in FP32; per-cell sums, the normalisation of Alg. 4 and the cell update are
+ * evaluated in FP64, and the integer decisions (slot offsets of Alg. 5, the resampling CDF of
+ * Alg. 7) on masses rounded to multiples of 2^-40 and summed exactly in 64-bit integers.
+ * DOGM_PRECISION_FP64: every real-valued array (each "FP32" array of dogm_views below, except
+ * the caller's measurement) holds FP64 and every step computes in FP64 (Box-Muller and the cell
+ * decision included), with the same exact integer decisions; the arena grows accordingly. */
+enum { DOGM_PRECISION_FP32 = 0, DOGM_PRECISION_FP64 = 1 };
 
 /* Size limits.  Masses are summed in 64-bit fixed point (units of 2^-40; every cell holds at
  * most mass 1), which cannot overflow for nx*ny < 2^24.  The systematic draws of Alg. 7 are
@@ -121,7 +131,8 @@ typedef struct dogm_meas {
     const float* det;
 } dogm_meas;
 
-/* Device pointers to every array of a grid (all inside the arena). */
+/* Device pointers to every array of a grid (all inside the arena).  The arrays typed float
+ * below hold double when the grid's precision is DOGM_PRECISION_FP64 (cast the pointer). */
 typedef struct dogm_views {
     /* persistent particles at the start of a cycle / after resampling (nu each) */
     float *x, *y, *vx, *vy, *w;

@@ -60,6 +60,7 @@ bool valid_params(const dogm_params* p)
     if (p->n_pers < 1 || p->n_pers >= (int64_t(1) << 27)) return false;
     if (p->n_born < 0 || p->n_born >= (int64_t(1) << 30)) return false;
     if (p->model != DOGM_MODEL_DS && p->model != DOGM_MODEL_PHD_MIB) return false;
+    if (p->precision != DOGM_PRECISION_FP32 && p->precision != DOGM_PRECISION_FP64) return false;
     return true;
 }
 
@@ -81,8 +82,9 @@ T* at(char* base, size_t off)
 }
 
 // The per-cycle scratch of a grid: digit histograms of every sort tile (digit-major) with their
-// row totals, fixed-point partial sums of new-born masses and of joint weights, first-slot marks
-// and the first cell of every new-born tile.  Every array is rewritten within each cycle before
+// row totals, fixed-point partial sums of new-born masses and of joint weights (turned into
+// exclusive prefixes in place, the total in one extra entry), first-slot marks and the first
+// cell of every new-born tile.  Every array is rewritten within each cycle before
 // it is read, so none needs clearing.  Places the arrays at `base` (sizes and tilings of d must
 // be set; base may be null to only measure) and returns the bytes they take.
 size_t place_scratch(GridDev& d, char* base)
@@ -90,9 +92,9 @@ size_t place_scratch(GridDev& d, char* base)
     Layout L;
     const size_t o_hist = L.take(4ull * kSortBins * d.n_hist_tiles);
     const size_t o_rowtot = L.take(4ull * kSortBins);
-    const size_t o_bpart = L.take(8ull * d.n_cell_parts);
+    const size_t o_bpart = L.take(8ull * (d.n_cell_parts + 1));
     const size_t o_mark = L.take(4ull * d.nb);
-    const size_t o_rpart = L.take(8ull * (d.n_res_ptiles + d.n_born_parts));
+    const size_t o_rpart = L.take(8ull * (d.n_res_ptiles + d.n_born_parts + 1));
     const size_t o_tfirst = L.take(4ull * d.n_born_parts);
     if (base) {
         d.hist = at<uint32_t>(base, o_hist);
@@ -129,6 +131,7 @@ GridDev describe(const dogm_params* p, char* base, size_t* bytes)
     d.seed_hi = (uint32_t)(p->seed >> 32);
     d.grid_id = p->grid_id;
     d.model = p->model;
+    d.real64 = p->precision == DOGM_PRECISION_FP64 ? 1u : 0u;
     // radix digits: as few passes of at most kSortBits bits as cover the largest key (C)
     const int kb = key_bits(C);
     d.passes = (uint32_t)((kb + kSortBits - 1) / kSortBits);
@@ -148,10 +151,13 @@ GridDev describe(const dogm_params* p, char* base, size_t* bytes)
 
     Layout L;
     L.take(sizeof(GridDev));
-    const size_t f_nu = 4ull * nu, f_nb = 4ull * nb, f_c = 4ull * C, d_c = 8ull * C;
+    const size_t f_nu = 4ull * nu, f_c = 4ull * C, d_c = 8ull * C;
+    // real-valued arrays: FP32, or FP64 in the all-FP64 precision mode
+    const size_t rb = d.real64 ? 8 : 4;
+    const size_t r_nu = rb * nu, r_nb = rb * nb, r_c = rb * C;
     float** pf_nu[] = {&d.x, &d.y, &d.vx, &d.vy, &d.w, &d.sx, &d.sy, &d.svx, &d.svy, &d.sw};
     size_t o_pf_nu[10];
-    for (int i = 0; i < 10; ++i) o_pf_nu[i] = L.take(f_nu);
+    for (int i = 0; i < 10; ++i) o_pf_nu[i] = L.take(r_nu);
     uint32_t** pu_nu[] = {&d.key, &d.skey, &d.perm, &d.tkey, &d.tval};
     size_t o_pu_nu[5];
     for (int i = 0; i < 5; ++i) o_pu_nu[i] = L.take(f_nu);
@@ -165,12 +171,12 @@ GridDev describe(const dogm_params* p, char* base, size_t* bytes)
     float** pf_c[] = {&d.m_pO, &d.m_pF, &d.m_O, &d.m_F, &d.rho_b, &d.rho_p, &d.pign,
                       &d.mean_x, &d.mean_y, &d.var_x, &d.var_y, &d.cov_xy};
     size_t o_pf_c[12];
-    for (int i = 0; i < 12; ++i) o_pf_c[i] = L.take(f_c);
+    for (int i = 0; i < 12; ++i) o_pf_c[i] = L.take(r_c);
     const size_t o_boff = L.take(4ull * (C + 1)), o_mfl = L.take(C);
     float** pf_nb[] = {&d.bx, &d.by, &d.bvx, &d.bvy, &d.bw};
     size_t o_pf_nb[5];
-    for (int i = 0; i < 5; ++i) o_pf_nb[i] = L.take(f_nb);
-    const size_t o_bkey = L.take(f_nb), o_bas = L.take(nb);
+    for (int i = 0; i < 5; ++i) o_pf_nb[i] = L.take(r_nb);
+    const size_t o_bkey = L.take(4ull * nb), o_bas = L.take(nb);
     const size_t o_scratch = L.take(place_scratch(d, nullptr));
     const size_t o_cyc = L.take(4), o_cycr = L.take(4), o_st = L.take(4), o_nc = L.take(4),
                  o_W = L.take(8), o_S = L.take(8);
@@ -534,11 +540,13 @@ int dogm_step_batch(dogm_grid* const* grids, const dogm_meas* meas, int n, dogm_
     }
     hipStream_t s = static_cast<hipStream_t>(stream);
     // one launch per kernel for up to kMaxBatch grids; grids with and without velocity
-    // evidence go to separate launches of the update
-    for (int kind = 0; kind < 2; ++kind) {
+    // evidence, and grids of the two precision modes, go to separate launches
+    for (int kind = 0; kind < 4; ++kind) {
+        const bool assoc = (kind & 1) != 0, real64 = (kind & 2) != 0;
         std::vector<GridRef> refs;
         for (int i = 0; i < n; ++i)
-            if ((meas[i].p_assoc != nullptr) == (kind == 1)) refs.push_back(grids[i]->ref(&meas[i]));
+            if ((meas[i].p_assoc != nullptr) == assoc && (grids[i]->hd.real64 != 0) == real64)
+                refs.push_back(grids[i]->ref(&meas[i]));
         for (size_t c0 = 0; c0 < refs.size(); c0 += kMaxBatch) {
             const int m = (int)std::min(refs.size() - c0, (size_t)kMaxBatch);
             const GridRef* r = refs.data() + c0;
@@ -558,7 +566,8 @@ int dogm_sensor_truth(const double* rects, int32_t n_rects, const uint8_t* stati
                       int32_t nx, int32_t ny, double cell_size, uint8_t* occ,
                       dogm_stream_t stream)
 {
-    if (nx < 1 || ny < 1 || (int64_t)nx * (int64_t)ny >= (int64_t(1) << 24) || !occ) return DOGM_EINVAL;
+    if (nx < 1 || ny < 1 || (int64_t)nx * (int64_t)ny >= (int64_t(1) << 24) || !occ)
+        return DOGM_EINVAL;
     if (n_rects < 0 || (n_rects > 0 && !rects)) return DOGM_EINVAL;
     if (!(std::isfinite(cell_size) && cell_size > 0.0)) return DOGM_EINVAL;
     const hipError_t e = launch_sensor_truth(rects, n_rects, static_occ, nx, ny, cell_size, occ,

@@ -86,6 +86,16 @@ using ConstPtr = __attribute__((address_space(4))) const T*;  // read-only while
 // 64-bit address pair per access.  Same size and bits as a plain pointer.
 using u32x4 = uint32_t __attribute__((ext_vector_type(4)));
 using f32x4 = float __attribute__((ext_vector_type(4)));
+using f64x2 = double __attribute__((ext_vector_type(2)));
+// A 16-byte vector of real values: four FP32 or two FP64 elements.
+template <typename R>
+struct RealVec16 {
+    using type = f32x4;
+};
+template <>
+struct RealVec16<double> {
+    using type = f64x2;
+};
 
 template <typename T>
 struct GArr {
@@ -115,6 +125,7 @@ struct GridT {
     float r, dt, p_s, p_b, sig_pos, sig_vel, sig_birth, alpha;
     uint32_t seed_lo, seed_hi, grid_id;
     uint32_t model;  // kModelPhdMib: Sec. V; otherwise the Dempster-Shafer model of Sec. VI
+    uint32_t real64;  // 1: the real-valued arrays hold FP64 (all-FP64 precision mode), else FP32
     // sort plan (from the largest key, C) and tilings
     uint32_t passes;
     uint32_t dshift[kMaxPasses], dbits[kMaxPasses];
@@ -143,7 +154,8 @@ struct GridT {
     // per-cycle scratch: digit histograms of every sort tile (digit-major,
     // [kSortBins][n_hist_tiles]) with their row totals, fixed-point partial sums of new-born
     // masses (per 256 cells) and of joint weights (per persistent resampling tile, then per
-    // new-born tile), the first slot of every cell with births (its cell id, kNoCell
+    // new-born tile), each array turned into exclusive prefixes in place with the total in one
+    // extra entry, the first slot of every cell with births (its cell id, kNoCell
     // elsewhere) and the cell of the first slot of every new-born tile
     P<uint32_t> hist, rowtot;
     P<uint64_t> bpart, rpart;
@@ -177,6 +189,15 @@ struct Batch {
     MeasDev m[kMaxBatch];
 };
 static_assert(sizeof(Batch) <= 4096, "a batch descriptor is one kernel argument");
+
+// Real-valued arrays (particle state; per-cell masses, normalised weights and moments) hold FP32
+// elements, or FP64 in the all-FP64 precision mode; their descriptor entries are typed as FP32
+// and kernels templated on the real type R see them through real<R>().
+template <typename R>
+__device__ __forceinline__ GArr<R> real(const GArr<float>& a)
+{
+    return GArr<R>{(GlobalPtr<R>)(GlobalPtr<void>)a.p};
+}
 
 // Private copies of a grid's descriptor and measurement with global-address-space pointers.
 // The descriptor is read through the constant address space (it is never written while a
@@ -293,21 +314,41 @@ __device__ __forceinline__ void box_muller_f32(float u1, float u2, float& n1, fl
     n2 = radius * __builtin_amdgcn_sinf(u2);
 }
 
-// Cell of an FP32 position: one correctly rounded FP32 division per axis, C outside the grid.
-__device__ __forceinline__ uint32_t cell_of(const GridView& G, float x, float y)
+// Box-Muller in FP64 (the all-FP64 precision mode), on the device's double-precision log,
+// square root, cosine and sine.
+__device__ __forceinline__ void box_muller_f64(double u1, double u2, double& n1, double& n2)
 {
-    const float fx = x / G.r;
-    const float fy = y / G.r;
-    if (!(fx >= 0.0f && fx < (float)G.nx && fy >= 0.0f && fy < (float)G.ny)) return G.C;
+    const double radius = sqrt(-2.0 * log(u1));
+    const double a = 6.283185307179586476925286766559 * u2;
+    n1 = radius * cos(a);
+    n2 = radius * sin(a);
+}
+
+template <typename R>
+__device__ __forceinline__ void box_muller(R u1, R u2, R& n1, R& n2)
+{
+    if constexpr (sizeof(R) == 8) box_muller_f64(u1, u2, n1, n2);
+    else box_muller_f32(u1, u2, n1, n2);
+}
+
+// Cell of a position: one correctly rounded division per axis in the position's precision, C
+// outside the grid.
+template <typename R>
+__device__ __forceinline__ uint32_t cell_of(const GridView& G, R x, R y)
+{
+    const R fx = x / (R)G.r;
+    const R fy = y / (R)G.r;
+    if (!(fx >= (R)0 && fx < (R)G.nx && fy >= (R)0 && fy < (R)G.ny)) return G.C;
     return (uint32_t)fy * (uint32_t)G.nx + (uint32_t)fx;
 }
 
-// Mass in fixed point: multiples of 2^-40, rounded to nearest (exact for FP32 input).
-__device__ __forceinline__ uint64_t fixed40(float m)
+// Mass in fixed point: multiples of 2^-40, rounded to nearest (halves up).
+__device__ __forceinline__ uint64_t fixed40(double m)
 {
-    if (!(m > 0.0f)) return 0;
-    return (uint64_t)floor((double)m * 0x1p40 + 0.5);
+    if (!(m > 0.0)) return 0;
+    return (uint64_t)floor(m * 0x1p40 + 0.5);
 }
+__device__ __forceinline__ uint64_t fixed40(float m) { return fixed40((double)m); }
 
 // --------------------------------------------------------------------------------------------
 // Wave- and block-level helpers (wave64).
@@ -386,6 +427,29 @@ __device__ __forceinline__ T block_sum(T v, T* lds)
     T total;
     block_excl_scan(v, lds, &total);
     return total;
+}
+
+// Sum of the partials part[0..limit) and of all n of them (one value per thread, block-wide).
+__device__ __forceinline__ void partials_before(const GArr<uint64_t>& part, uint32_t n,
+                                                uint32_t limit, uint64_t* tmp, uint64_t* before,
+                                                uint64_t* all)
+{
+    uint64_t bsum = 0, asum = 0;
+    for (uint32_t t0 = threadIdx.x; t0 < n; t0 += 4 * blockDim.x) {
+        uint64_t v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const uint32_t t = t0 + u * blockDim.x;
+            v[u] = t < n ? part[t] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            asum += v[u];
+            if (t0 + u * blockDim.x < limit) bsum += v[u];
+        }
+    }
+    *before = block_sum(bsum, tmp);
+    *all = block_sum(asum, tmp);
 }
 
 }  // namespace dogm

@@ -31,10 +31,11 @@ constexpr uint32_t kNone = 0xFFFFFFFFu;
 // The wave finds its first cell from the keys (the first particle whose cell differs from the
 // one before the wave's share) and finishes the cell of its last particle past its share.
 // kRanges: also store the range of every cell it handles.
-template <int NV, bool kRanges, typename Val, typename Emit>
+template <int NV, bool kRanges, typename R, typename Val, typename Emit>
 __device__ __forceinline__ void seg_reduce(const GridView& G, uint32_t wave_index, Val val,
                                            Emit emit)
 {
+    const auto SW = real<R>(G.sw), SVX = real<R>(G.svx), SVY = real<R>(G.svy);
     const int lane = lane_id();
     const uint32_t n = G.nu, C = G.C;
     const uint32_t a = wave_index * kSegRange;
@@ -44,7 +45,7 @@ __device__ __forceinline__ void seg_reduce(const GridView& G, uint32_t wave_inde
     // chunks of kSegRange particles at fixed offsets from a; the first chunk is read while the
     // wave's first cell is looked up (particles before p0 are masked out below)
     uint32_t key[kSegItems];
-    float pw[kSegItems], pvx[kSegItems], pvy[kSegItems];
+    R pw[kSegItems], pvx[kSegItems], pvy[kSegItems];
     auto load_keys = [&](uint32_t base, uint32_t bound) {
         const uint32_t i0 = base + lane * kSegItems;
         if (i0 + kSegItems <= bound) {  // a lane's items are whole 16-byte vectors
@@ -63,13 +64,16 @@ __device__ __forceinline__ void seg_reduce(const GridView& G, uint32_t wave_inde
     auto load_state = [&](uint32_t base, uint32_t bound) {
         const uint32_t i0 = base + lane * kSegItems;
         if (i0 + kSegItems <= bound) {
+            // 16-byte vectors: four FP32 or two FP64 elements
+            using V = typename RealVec16<R>::type;
+            constexpr int kVec = 16 / (int)sizeof(R);
 #pragma unroll
-            for (int q = 0; q < kSegItems; q += 4) {
-                const f32x4 w4 = G.sw.load_vec<f32x4>(i0 + q);
-                const f32x4 x4 = G.svx.load_vec<f32x4>(i0 + q);
-                const f32x4 y4 = G.svy.load_vec<f32x4>(i0 + q);
+            for (int q = 0; q < kSegItems; q += kVec) {
+                const V w4 = SW.template load_vec<V>(i0 + q);
+                const V x4 = SVX.template load_vec<V>(i0 + q);
+                const V y4 = SVY.template load_vec<V>(i0 + q);
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
+                for (int e = 0; e < kVec; ++e) {
                     pw[q + e] = w4[e];
                     pvx[q + e] = x4[e];
                     pvy[q + e] = y4[e];
@@ -79,9 +83,9 @@ __device__ __forceinline__ void seg_reduce(const GridView& G, uint32_t wave_inde
 #pragma unroll
             for (int it = 0; it < kSegItems; ++it) {
                 const uint32_t i = i0 + it;
-                pw[it] = (i < bound) ? G.sw[i] : 0.0f;
-                pvx[it] = (i < bound) ? G.svx[i] : 0.0f;
-                pvy[it] = (i < bound) ? G.svy[i] : 0.0f;
+                pw[it] = (i < bound) ? SW[i] : (R)0;
+                pvx[it] = (i < bound) ? SVX[i] : (R)0;
+                pvy[it] = (i < bound) ? SVY[i] : (R)0;
             }
         }
     };
@@ -161,7 +165,7 @@ __device__ __forceinline__ void seg_reduce(const GridView& G, uint32_t wave_inde
             }
             if (k != kNone) {
                 double v[NV];
-                val(k, pw[it], pvx[it], pvy[it], v);
+                val(k, (double)pw[it], (double)pvx[it], (double)pvy[it], v);
 #pragma unroll
                 for (int j = 0; j < NV; ++j) acc[j] += v[j];
             }
@@ -254,8 +258,9 @@ __device__ __forceinline__ double likelihood(double vx, double vy, double mx, do
 // (pred_birth_prob)); every weight of the cell is scaled by the factor of eqs.
 // (updateParticleWeightsUnnormalized), (applyNormalization), (normalizationCalculation) after a
 // measurement, of eq. (updateParticleWeightsEmpty) without one.  Same outputs as cell_update.
+template <typename R>
 __device__ __forceinline__ double cell_update_phd(const GridView& G, const MeasView& M,
-                                                  uint32_t c, double s, float* rb_out)
+                                                  uint32_t c, double s, R* rb_out)
 {
     const double rp = s < 1.0 ? s : 1.0;
     const double rb_pred = (double)G.p_b * (1.0 - rp);
@@ -265,25 +270,26 @@ __device__ __forceinline__ double cell_update_phd(const GridView& G, const MeasV
                                       : (1.0 - tp) / ((1.0 - tp) * r + (1.0 - fp) * (1.0 - r));
     const double o = f * r, rho_p = f * rp, rb = f * rb_pred;
     if (!isfinite(f) || !isfinite(s)) status_or(G, kStNonFinite);
-    G.m_pO[c] = (float)rp;
-    G.m_pF[c] = (float)(1.0 - r);
-    G.m_O[c] = (float)o;
-    G.m_F[c] = (float)(1.0 - o);
-    G.rho_b[c] = (float)rb;
-    G.rho_p[c] = (float)rho_p;
-    G.pign[c] = (float)o;
+    real<R>(G.m_pO)[c] = (R)rp;
+    real<R>(G.m_pF)[c] = (R)(1.0 - r);
+    real<R>(G.m_O)[c] = (R)o;
+    real<R>(G.m_F)[c] = (R)(1.0 - o);
+    real<R>(G.rho_b)[c] = (R)rb;
+    real<R>(G.rho_p)[c] = (R)rho_p;
+    real<R>(G.pign)[c] = (R)o;
     G.mu_UA[c] = s > 0.0 ? rho_p / s : 0.0;
     G.mu_A[c] = G.mu_UA[c];
-    *rb_out = (float)rb;
+    *rb_out = (R)rb;
     return rho_p;
 }
 
+template <typename R>
 __device__ __forceinline__ double cell_update(const GridView& G, const MeasView& M, uint32_t c,
-                                              double s, double st, float* rb_out)
+                                              double s, double st, R* rb_out)
 {
-    if (G.model == kModelPhdMib) return cell_update_phd(G, M, c, s, rb_out);
+    if (G.model == kModelPhdMib) return cell_update_phd<R>(G, M, c, s, rb_out);
     const double po = s < 1.0 ? s : 1.0;
-    const double pf_cand = (double)G.alpha * (double)G.m_F[c];
+    const double pf_cand = (double)G.alpha * (double)real<R>(G.m_F)[c];
     const double pf = pf_cand < 1.0 - po ? pf_cand : 1.0 - po;
     const double zo = (double)M.m_occ[c], zf = (double)M.m_free[c];
     // Dempster's rule on {O, F}: conflict K = o1 f2 + f1 o2
@@ -308,38 +314,40 @@ __device__ __forceinline__ double cell_update(const GridView& G, const MeasView&
     }
     const double rp = o - rb;
     if (!isfinite(o) || !isfinite(f) || !isfinite(s)) st_bits |= kStNonFinite;
-    G.m_pO[c] = (float)po;
-    G.m_pF[c] = (float)pf;
-    G.m_O[c] = (float)o;
-    G.m_F[c] = (float)f;
-    G.rho_b[c] = (float)rb;
-    G.rho_p[c] = (float)rp;
-    G.pign[c] = (float)(o + 0.5 * (1.0 - o - f));
+    real<R>(G.m_pO)[c] = (R)po;
+    real<R>(G.m_pF)[c] = (R)pf;
+    real<R>(G.m_O)[c] = (R)o;
+    real<R>(G.m_F)[c] = (R)f;
+    real<R>(G.rho_b)[c] = (R)rb;
+    real<R>(G.rho_p)[c] = (R)rp;
+    real<R>(G.pign)[c] = (R)(o + 0.5 * (1.0 - o - f));
     G.mu_UA[c] = s > 0.0 ? rp / s : 0.0;
     G.mu_A[c] = st > 0.0 ? rp / st : 0.0;
     if (st_bits) status_or(G, st_bits);
-    *rb_out = (float)rb;
+    *rb_out = (R)rb;
     return rp;
 }
 
 // Moments are defined where the stored rho_p is positive and the cell holds particles (the
 // caller decides); sums over weights that are all zero give zero moments.
+template <typename R>
 __device__ __forceinline__ void write_moments(const GridView& G, uint32_t c, bool defined,
                                               double norm, double sx, double sy, double sxx,
                                               double syy, double sxy)
 {
     if (!defined || !(norm > 0.0)) {
-        G.mean_x[c] = G.mean_y[c] = G.var_x[c] = G.var_y[c] = G.cov_xy[c] = 0.0f;
+        real<R>(G.mean_x)[c] = real<R>(G.mean_y)[c] = (R)0;
+        real<R>(G.var_x)[c] = real<R>(G.var_y)[c] = real<R>(G.cov_xy)[c] = (R)0;
         G.mflag[c] = defined ? 1 : 0;
         return;
     }
     const double inv = 1.0 / norm;
     const double mx = sx * inv, my = sy * inv;
-    G.mean_x[c] = (float)mx;
-    G.mean_y[c] = (float)my;
-    G.var_x[c] = (float)(sxx * inv - mx * mx);
-    G.var_y[c] = (float)(syy * inv - my * my);
-    G.cov_xy[c] = (float)(sxy * inv - mx * my);
+    real<R>(G.mean_x)[c] = (R)mx;
+    real<R>(G.mean_y)[c] = (R)my;
+    real<R>(G.var_x)[c] = (R)(sxx * inv - mx * mx);
+    real<R>(G.var_y)[c] = (R)(syy * inv - my * my);
+    real<R>(G.cov_xy)[c] = (R)(sxy * inv - mx * my);
     G.mflag[c] = 1;
 }
 
@@ -350,7 +358,7 @@ __device__ __forceinline__ void write_moments(const GridView& G, uint32_t c, boo
 // With evidence (launched by the update): the sums of w and of g w (Alg. 3, Alg. 4).
 // ----------------------------------------------------------------------------------------------
 
-template <bool kAssoc>
+template <bool kAssoc, typename R>
 __global__ __launch_bounds__(kSegThreads) void k_seg_sums(Batch b)
 {
     const int gi = batch_grid(b);
@@ -359,9 +367,9 @@ __global__ __launch_bounds__(kSegThreads) void k_seg_sums(Batch b)
     const uint32_t tile = xcd_tile(b, gi);
     const uint32_t wave = tile * (kSegThreads / kWave) + threadIdx.x / kWave;
     if (kAssoc) {
-        seg_reduce<2, false>(
+        seg_reduce<2, false, R>(
             G, wave,
-            [&](uint32_t k, float w, float vx, float vy, double* v) {
+            [&](uint32_t k, double w, double vx, double vy, double* v) {
                 v[0] = (double)w;
                 v[1] = likelihood((double)vx, (double)vy, (double)M.mu_vx[k],
                                   (double)M.mu_vy[k], (double)M.var_v[k]) * (double)w;
@@ -371,10 +379,10 @@ __global__ __launch_bounds__(kSegThreads) void k_seg_sums(Batch b)
                 G.sum_wt[k] = v[1];
             });
     } else {
-        seg_reduce<6, true>(
+        seg_reduce<6, true, R>(
             G, wave,
-            [&](uint32_t, float w, float vx, float vy, double* v) {
-                const double wd = (double)w, x = (double)vx, y = (double)vy;
+            [&](uint32_t, double w, double vx, double vy, double* v) {
+                const double wd = w, x = vx, y = vy;
                 v[0] = wd;
                 v[1] = wd * x;
                 v[2] = wd * y;
@@ -395,7 +403,7 @@ __global__ __launch_bounds__(kSegThreads) void k_seg_sums(Batch b)
 // velocity evidence); each block also stores the fixed-point new-born mass of its cells.
 // ----------------------------------------------------------------------------------------------
 
-template <bool kAssoc>
+template <bool kAssoc, typename R>
 __global__ __launch_bounds__(kCellThreads) void k_cells(Batch b)
 {
     __shared__ uint64_t tmp[kCellThreads / kWave + 1];
@@ -420,12 +428,14 @@ __global__ __launch_bounds__(kCellThreads) void k_cells(Batch b)
             G.sum_w[c] = 0.0;
             if (kAssoc) G.sum_wt[c] = 0.0;
         }
-        float rb;
-        const double rp = cell_update(G, M, c, s, st, &rb);
+        R rb;
+        const double rp = cell_update<R>(G, M, c, s, st, &rb);
         // moments of the updated weights mu_UA w, normalised by rho_p = mu_UA sum w; with
         // velocity evidence those of cells with particles come from their own pass
-        if (!kAssoc) write_moments(G, c, has && (float)rp > 0.0f, s, m[0], m[1], m[2], m[3], m[4]);
-        else if (!has) write_moments(G, c, false, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0);
+        if (!kAssoc)
+            write_moments<R>(G, c, has && (R)rp > (R)0, s, m[0], m[1], m[2], m[3], m[4]);
+        else if (!has)
+            write_moments<R>(G, c, false, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0);
         q = fixed40(rb);
     }
     const uint64_t qsum = block_sum(q, tmp);
@@ -438,7 +448,14 @@ hipError_t launch_cell_sums(const GridRef* g, int n, hipStream_t s)
     const uint32_t blocks = make_batch(b, g, n, [](const GridDev& G) {
         return xcd_blocks(ceil_div(G.nu, kSegBlockParticles));
     });
-    if (blocks) DOGM_LAUNCH(k_seg_sums<false>, dim3(blocks), dim3(kSegThreads), 0, s, b);
+    if (blocks) {
+        if (launch_real64(g, n))
+            DOGM_LAUNCH_AS("k_seg_sums<false>", (k_seg_sums<false, double>),
+                           dim3(blocks), dim3(kSegThreads), 0, s, b);
+        else
+            DOGM_LAUNCH_AS("k_seg_sums<false>", (k_seg_sums<false, float>),
+                           dim3(blocks), dim3(kSegThreads), 0, s, b);
+    }
     return hipGetLastError();
 }
 
@@ -450,20 +467,37 @@ hipError_t launch_update(const GridRef* g, int n, hipStream_t s)
         all_assoc &= g[i].m.p_assoc != nullptr;
     }
     if (any_assoc && !all_assoc) return hipErrorInvalidValue;  // one kind per launch
+    const bool real64 = launch_real64(g, n);
     Batch b;
     uint32_t blocks = 0;
     if (any_assoc) {  // without evidence the assignment already formed the sums
         blocks = make_batch(b, g, n, [](const GridDev& G) {
             return xcd_blocks(ceil_div(G.nu, kSegBlockParticles));
         });
-        if (blocks) DOGM_LAUNCH(k_seg_sums<true>, dim3(blocks), dim3(kSegThreads), 0, s, b);
+        if (blocks) {
+            if (real64)
+                DOGM_LAUNCH_AS("k_seg_sums<true>", (k_seg_sums<true, double>),
+                               dim3(blocks), dim3(kSegThreads), 0, s, b);
+            else
+                DOGM_LAUNCH_AS("k_seg_sums<true>", (k_seg_sums<true, float>),
+                               dim3(blocks), dim3(kSegThreads), 0, s, b);
+        }
     }
     blocks = make_batch(b, g, n, [](const GridDev& G) { return G.n_cell_parts; });
     if (blocks) {
-        if (any_assoc)
-            DOGM_LAUNCH(k_cells<true>, dim3(blocks), dim3(kCellThreads), 0, s, b);
+        const dim3 grid(blocks), block(kCellThreads);
+        if (any_assoc && real64)
+            DOGM_LAUNCH_AS("k_cells<true>", (k_cells<true, double>), grid, block,
+                           0, s, b);
+        else if (any_assoc)
+            DOGM_LAUNCH_AS("k_cells<true>", (k_cells<true, float>), grid, block,
+                           0, s, b);
+        else if (real64)
+            DOGM_LAUNCH_AS("k_cells<false>", (k_cells<false, double>), grid, block,
+                           0, s, b);
         else
-            DOGM_LAUNCH(k_cells<false>, dim3(blocks), dim3(kCellThreads), 0, s, b);
+            DOGM_LAUNCH_AS("k_cells<false>", (k_cells<false, float>), grid, block,
+                           0, s, b);
     }
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = launch_born_offsets(g, n, s);
@@ -475,16 +509,17 @@ hipError_t launch_update(const GridRef* g, int n, hipStream_t s)
 // Alg. 6 with velocity evidence: moments of the updated weights, normalised by rho_p.
 // ----------------------------------------------------------------------------------------------
 
+template <typename R>
 __global__ __launch_bounds__(kSegThreads) void k_seg_moments(Batch b)
 {
     const int gi = batch_grid(b);
     const GridView G = grid_view(b.g[gi]);
     const uint32_t tile = xcd_tile(b, gi);
     const uint32_t wave = tile * (kSegThreads / kWave) + threadIdx.x / kWave;
-    seg_reduce<5, false>(
+    seg_reduce<5, false, R>(
         G, wave,
-        [&](uint32_t, float w, float vx, float vy, double* v) {
-            const double wd = (double)w, x = (double)vx, y = (double)vy;
+        [&](uint32_t, double w, double vx, double vy, double* v) {
+            const double wd = w, x = vx, y = vy;
             v[0] = wd * x;
             v[1] = wd * y;
             v[2] = wd * x * x;
@@ -492,8 +527,8 @@ __global__ __launch_bounds__(kSegThreads) void k_seg_moments(Batch b)
             v[4] = wd * x * y;
         },
         [&](uint32_t k, const double* v) {
-            const double rp = (double)G.rho_p[k];
-            write_moments(G, k, rp > 0.0, rp, v[0], v[1], v[2], v[3], v[4]);
+            const double rp = (double)real<R>(G.rho_p)[k];
+            write_moments<R>(G, k, rp > 0.0, rp, v[0], v[1], v[2], v[3], v[4]);
         });
 }
 
@@ -509,7 +544,9 @@ hipError_t launch_moments(const GridRef* g, int n, hipStream_t s)
     const uint32_t blocks = make_batch(b, sub, m, [](const GridDev& G) {
         return xcd_blocks(ceil_div(G.nu, kSegBlockParticles));
     });
-    if (blocks) DOGM_LAUNCH(k_seg_moments, dim3(blocks), dim3(kSegThreads), 0, s, b);
+    if (blocks)
+        DOGM_LAUNCH_REAL(launch_real64(sub, m), "k_seg_moments", k_seg_moments, dim3(blocks),
+                         dim3(kSegThreads), 0, s, b);
     return hipGetLastError();
 }
 

@@ -17,6 +17,7 @@ hipError_t launch_write_desc(const GridDev& hd, GridDev* dd, hipStream_t s)
 // Initial state: particles uniform over the grid, velocity N(0, sigma_B^2), weight 0; m_F = 0.
 // ----------------------------------------------------------------------------------------------
 
+template <typename R>
 __global__ __launch_bounds__(kElemThreads) void k_init(Batch b)
 {
     const int gi = batch_grid(b);
@@ -24,15 +25,15 @@ __global__ __launch_bounds__(kElemThreads) void k_init(Batch b)
     const uint32_t i = (blockIdx.x - b.bstart[gi]) * kElemThreads + threadIdx.x;
     if (i < G.nu) {
         const uint4 r = draw(G, i, 0u, kPurposeInit);
-        float n0, n1;
-        box_muller_f32(unit_f32(r.z), unit_f32(r.w), n0, n1);
-        G.x[i] = unit_f32(r.x) * ((float)G.nx * G.r);
-        G.y[i] = unit_f32(r.y) * ((float)G.ny * G.r);
-        G.vx[i] = G.sig_birth * n0;
-        G.vy[i] = G.sig_birth * n1;
-        G.w[i] = 0.0f;
+        R n0, n1;
+        box_muller<R>((R)unit_f32(r.z), (R)unit_f32(r.w), n0, n1);
+        real<R>(G.x)[i] = (R)unit_f32(r.x) * (R)G.nx * (R)G.r;
+        real<R>(G.y)[i] = (R)unit_f32(r.y) * (R)G.ny * (R)G.r;
+        real<R>(G.vx)[i] = (R)G.sig_birth * n0;
+        real<R>(G.vy)[i] = (R)G.sig_birth * n1;
+        real<R>(G.w)[i] = (R)0;
     }
-    if (i < G.C) G.m_F[i] = 0.0f;
+    if (i < G.C) real<R>(G.m_F)[i] = (R)0;
     if (i == 0) {
         *G.cycle = 1u;
         *G.cycle_run = 1u;
@@ -49,7 +50,9 @@ hipError_t launch_init(const GridRef* g, int n, hipStream_t s)
     const uint32_t blocks = make_batch(b, g, n, [](const GridDev& G) {
         return ceil_div(G.nu > G.C ? G.nu : G.C, kElemThreads);
     });
-    if (blocks) DOGM_LAUNCH(k_init, dim3(blocks), dim3(kElemThreads), 0, s, b);
+    if (blocks)
+        DOGM_LAUNCH_REAL(launch_real64(g, n), "k_init", k_init, dim3(blocks), dim3(kElemThreads),
+                         0, s, b);
     return hipGetLastError();
 }
 
@@ -79,6 +82,7 @@ hipError_t launch_set_cycle(const GridRef* g, int n, uint32_t cycle, hipStream_t
 
 constexpr int kPredItems = kHistTile / kHistThreads;  // 4
 
+template <typename R>
 __global__ __launch_bounds__(kHistThreads) void k_predict(Batch b)
 {
     __shared__ uint32_t cnt[kSortBins];
@@ -88,6 +92,8 @@ __global__ __launch_bounds__(kHistThreads) void k_predict(Batch b)
     if (tile >= G.n_hist_tiles) return;
     const uint32_t cycle = *G.cycle;
     const uint32_t shift = G.dshift[0], bits = G.dbits[0], nbins = 1u << bits;
+    const auto X = real<R>(G.x), Y = real<R>(G.y), VX = real<R>(G.vx), VY = real<R>(G.vy);
+    const auto Wt = real<R>(G.w);
 
     const uint32_t nthreads = G.n_hist_tiles * kHistThreads;
     const uint32_t tid = tile * kHistThreads + threadIdx.x;
@@ -101,16 +107,16 @@ __global__ __launch_bounds__(kHistThreads) void k_predict(Batch b)
     for (uint32_t d = threadIdx.x; d < nbins; d += kHistThreads) cnt[d] = 0;
     __syncthreads();
 
-    float x[kPredItems], y[kPredItems], vx[kPredItems], vy[kPredItems], w[kPredItems];
+    R x[kPredItems], y[kPredItems], vx[kPredItems], vy[kPredItems], w[kPredItems];
 #pragma unroll
     for (int it = 0; it < kPredItems; ++it) {
         const uint32_t i = tile * kHistTile + it * kHistThreads + threadIdx.x;
         const bool valid = i < G.nu;
-        x[it] = valid ? G.x[i] : 0.0f;
-        y[it] = valid ? G.y[i] : 0.0f;
-        vx[it] = valid ? G.vx[i] : 0.0f;
-        vy[it] = valid ? G.vy[i] : 0.0f;
-        w[it] = valid ? G.w[i] : 0.0f;
+        x[it] = valid ? X[i] : (R)0;
+        y[it] = valid ? Y[i] : (R)0;
+        vx[it] = valid ? VX[i] : (R)0;
+        vy[it] = valid ? VY[i] : (R)0;
+        w[it] = valid ? Wt[i] : (R)0;
     }
 #pragma unroll
     for (int it = 0; it < kPredItems; ++it) {
@@ -119,19 +125,19 @@ __global__ __launch_bounds__(kHistThreads) void k_predict(Batch b)
         uint32_t k = 0;
         if (valid) {
             const uint4 r = draw(G, i, cycle, kPurposePredict);
-            float n0, n1, n2, n3;
-            box_muller_f32(unit_f32(r.x), unit_f32(r.y), n0, n1);
-            box_muller_f32(unit_f32(r.z), unit_f32(r.w), n2, n3);
-            const float xn = x[it] + G.dt * vx[it] + G.sig_pos * n0;
-            const float yn = y[it] + G.dt * vy[it] + G.sig_pos * n1;
-            const float vxn = vx[it] + G.sig_vel * n2;
-            const float vyn = vy[it] + G.sig_vel * n3;
-            k = cell_of(G, xn, yn);
-            G.x[i] = xn;
-            G.y[i] = yn;
-            G.vx[i] = vxn;
-            G.vy[i] = vyn;
-            G.w[i] = (k == G.C) ? 0.0f : G.p_s * w[it];
+            R n0, n1, n2, n3;
+            box_muller<R>((R)unit_f32(r.x), (R)unit_f32(r.y), n0, n1);
+            box_muller<R>((R)unit_f32(r.z), (R)unit_f32(r.w), n2, n3);
+            const R xn = x[it] + (R)G.dt * vx[it] + (R)G.sig_pos * n0;
+            const R yn = y[it] + (R)G.dt * vy[it] + (R)G.sig_pos * n1;
+            const R vxn = vx[it] + (R)G.sig_vel * n2;
+            const R vyn = vy[it] + (R)G.sig_vel * n3;
+            k = cell_of<R>(G, xn, yn);
+            X[i] = xn;
+            Y[i] = yn;
+            VX[i] = vxn;
+            VY[i] = vyn;
+            Wt[i] = (k == G.C) ? (R)0 : (R)G.p_s * w[it];
             G.key[i] = k;
         }
         digit_count(valid, (k >> shift) & (nbins - 1u), cnt);
@@ -146,7 +152,9 @@ hipError_t launch_predict(const GridRef* g, int n, hipStream_t s)
     Batch b;
     const uint32_t blocks =
         make_batch(b, g, n, [](const GridDev& G) { return xcd_blocks(G.n_hist_tiles); });
-    if (blocks) DOGM_LAUNCH(k_predict, dim3(blocks), dim3(kHistThreads), 0, s, b);
+    if (blocks)
+        DOGM_LAUNCH_REAL(launch_real64(g, n), "k_predict", k_predict, dim3(blocks),
+                         dim3(kHistThreads), 0, s, b);
     return hipGetLastError();
 }
 
@@ -170,31 +178,79 @@ __device__ __forceinline__ uint32_t slot_offset(uint64_t E, uint64_t S, uint32_t
     return o > (double)nb ? nb : (uint32_t)o;
 }
 
-__global__ __launch_bounds__(kCellThreads) void k_born_offsets(Batch b)
+// Exclusive prefix sums, in place, of a grid's fixed-point partial sums: the new-born masses
+// per block of cells (which = 0; total S) or the joint weights per resampling tile (which = 1;
+// total W), the total also in the extra last entry and in the grid's device scalar.  One block
+// per grid, so every block that consumes the partials reads one word instead of adding up all
+// the partials before its own (launched for grids with many partials only).
+constexpr int kScanPartThreads = 1024;
+constexpr int kScanPartItems = 4;
+
+__global__ __launch_bounds__(kScanPartThreads) void k_scan_parts(Batch b, int which)
+{
+    __shared__ uint64_t tmp[kScanPartThreads / kWave + 1];
+    const GridView G = grid_view(b.g[blockIdx.x]);
+    const GArr<uint64_t> a = which == 0 ? G.bpart : G.rpart;
+    const uint32_t n = which == 0 ? G.n_cell_parts : G.n_res_ptiles + G.n_born_parts;
+    uint64_t carry = 0;
+    for (uint32_t base = 0; base < n; base += kScanPartThreads * kScanPartItems) {
+        const uint32_t t0 = base + threadIdx.x * kScanPartItems;
+        uint64_t v[kScanPartItems], acc = 0;
+#pragma unroll
+        for (int j = 0; j < kScanPartItems; ++j) {
+            v[j] = t0 + j < n ? a[t0 + j] : 0;
+            acc += v[j];
+        }
+        uint64_t total;
+        uint64_t run = carry + block_excl_scan(acc, tmp, &total);
+#pragma unroll
+        for (int j = 0; j < kScanPartItems; ++j) {
+            if (t0 + j < n) a[t0 + j] = run;
+            run += v[j];
+        }
+        carry += total;
+    }
+    if (threadIdx.x == 0) {
+        a[n] = carry;
+        if (which == 0) *G.S_fixed = carry;
+        else *G.W_fixed = carry;
+    }
+}
+
+hipError_t launch_scan_parts(const GridRef* g, int n, int which, bool* prefixed, hipStream_t s)
+{
+    uint32_t most = 0;
+    for (int i = 0; i < n; ++i) {
+        const GridDev& G = *g[i].hd;
+        const uint32_t parts = which == 0 ? G.n_cell_parts : G.n_res_ptiles + G.n_born_parts;
+        most = parts > most ? parts : most;
+    }
+    *prefixed = most > kScanPartsFrom;
+    if (!*prefixed) return hipSuccess;
+    Batch b;
+    const uint32_t blocks = make_batch(b, g, n, [](const GridDev&) { return 1u; });
+    if (blocks) DOGM_LAUNCH(k_scan_parts, dim3(blocks), dim3(kScanPartThreads), 0, s, b, which);
+    return hipGetLastError();
+}
+
+template <typename R>
+__global__ __launch_bounds__(kCellThreads) void k_born_offsets(Batch b, int prefixed)
 {
     __shared__ uint64_t tmp[kCellThreads / kWave + 1];
     const int gi = batch_grid(b);
     const GridView G = grid_view(b.g[gi]);
     const uint32_t part = blockIdx.x - b.bstart[gi];
     const uint32_t c = part * kCellThreads + threadIdx.x;
-    const float rb = (c < G.C) ? G.rho_b[c] : 0.0f;  // read while the prefix is formed
-    uint64_t before = 0, all = 0;
-    for (uint32_t t0 = threadIdx.x; t0 < G.n_cell_parts; t0 += 4 * kCellThreads) {
-        uint64_t v[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const uint32_t t = t0 + u * kCellThreads;
-            v[u] = t < G.n_cell_parts ? G.bpart[t] : 0;
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            all += v[u];
-            if (t0 + u * kCellThreads < part) before += v[u];
-        }
+    const R rb = (c < G.C) ? real<R>(G.rho_b)[c] : (R)0;
+    // new-born mass of the cell blocks before this one, and in total
+    uint64_t before, Stot;
+    if (prefixed) {
+        before = G.bpart[part];
+        Stot = *G.S_fixed;
+    } else {
+        partials_before(G.bpart, G.n_cell_parts, part, tmp, &before, &Stot);
+        if (part == 0 && threadIdx.x == 0) *G.S_fixed = Stot;
     }
-    before = block_sum(before, tmp);
-    const uint64_t Stot = block_sum(all, tmp);
-    if (part == 0 && threadIdx.x == 0) *G.S_fixed = Stot;
     const uint64_t q = fixed40(rb);
     uint64_t total;
     const uint64_t E = before + block_excl_scan(q, tmp, &total);
@@ -237,10 +293,14 @@ __global__ __launch_bounds__(kCellThreads) void k_born_offsets(Batch b)
 
 hipError_t launch_born_offsets(const GridRef* g, int n, hipStream_t s)
 {
+    bool prefixed = false;
+    if (const hipError_t e = launch_scan_parts(g, n, 0, &prefixed, s); e != hipSuccess) return e;
     Batch b;
     const uint32_t blocks =
         make_batch(b, g, n, [](const GridDev& G) { return ceil_div(G.C + 1, kCellThreads); });
-    if (blocks) DOGM_LAUNCH(k_born_offsets, dim3(blocks), dim3(kCellThreads), 0, s, b);
+    if (blocks)
+        DOGM_LAUNCH_REAL(launch_real64(g, n), "k_born_offsets", k_born_offsets, dim3(blocks),
+                         dim3(kCellThreads), 0, s, b, prefixed ? 1 : 0);
     return hipGetLastError();
 }
 
@@ -259,8 +319,9 @@ __device__ __forceinline__ double likelihood(double vx, double vy, double mx, do
 }
 
 // Initialises new-born slot s of cell c (born_off[c] <= s < born_off[c+1]); returns its weight.
-__device__ __forceinline__ float init_born(const GridView& G, const MeasView& M, uint32_t s,
-                                          uint32_t c, uint32_t cycle)
+template <typename R>
+__device__ __forceinline__ R init_born(const GridView& G, const MeasView& M, uint32_t s,
+                                      uint32_t c, uint32_t cycle)
 {
     const uint32_t o0 = G.born_off[c], o1 = G.born_off[c + 1];
     const uint32_t n_c = o1 - o0;
@@ -268,31 +329,32 @@ __device__ __forceinline__ float init_born(const GridView& G, const MeasView& M,
     const uint32_t na = (uint32_t)floor(__dadd_rn(__dmul_rn(pa, (double)n_c), 0.5));
     const uint32_t nua = n_c - na;
     const bool assoc = (s - o0) < na;
-    const double rb = (double)G.rho_b[c];
+    const double rb = (double)real<R>(G.rho_b)[c];
     double w;
     if (assoc) w = (nua == 0) ? rb / (double)na : pa * rb / (double)na;
     else w = (na == 0) ? rb / (double)nua : (1.0 - pa) * rb / (double)nua;
     const uint4 r = draw(G, s, cycle, kPurposeBirth);
-    float n0, n1;
-    box_muller_f32(unit_f32(r.z), unit_f32(r.w), n0, n1);
+    R n0, n1;
+    box_muller<R>((R)unit_f32(r.z), (R)unit_f32(r.w), n0, n1);
     const uint32_t ix = c % (uint32_t)G.nx, iy = c / (uint32_t)G.nx;
-    G.bx[s] = ((float)ix + unit_f32(r.x)) * G.r;
-    G.by[s] = ((float)iy + unit_f32(r.y)) * G.r;
+    real<R>(G.bx)[s] = ((R)ix + (R)unit_f32(r.x)) * (R)G.r;
+    real<R>(G.by)[s] = ((R)iy + (R)unit_f32(r.y)) * (R)G.r;
     if (assoc) {
-        const float sd = sqrtf(M.var_v[c]);
-        G.bvx[s] = M.mu_vx[c] + sd * n0;
-        G.bvy[s] = M.mu_vy[c] + sd * n1;
+        const R sd = sqrt((R)M.var_v[c]);
+        real<R>(G.bvx)[s] = (R)M.mu_vx[c] + sd * n0;
+        real<R>(G.bvy)[s] = (R)M.mu_vy[c] + sd * n1;
     } else {
-        G.bvx[s] = G.sig_birth * n0;
-        G.bvy[s] = G.sig_birth * n1;
+        real<R>(G.bvx)[s] = (R)G.sig_birth * n0;
+        real<R>(G.bvy)[s] = (R)G.sig_birth * n1;
     }
-    const float wf = (float)w;
-    G.bw[s] = wf;
+    const R wr = (R)w;
+    real<R>(G.bw)[s] = wr;
     G.bkey[s] = c;
     G.bassoc[s] = assoc ? 1 : 0;
-    return wf;
+    return wr;
 }
 
+template <typename R>
 __global__ __launch_bounds__(kResThreads) void k_particle_tiles(Batch b)
 {
     __shared__ uint64_t tmp[kResThreads / kWave + 1];
@@ -307,14 +369,15 @@ __global__ __launch_bounds__(kResThreads) void k_particle_tiles(Batch b)
     uint64_t q = 0;
     if (tile < pblocks) {
         // kPtSplit resampling tiles; items [h * kResItems, (h + 1) * kResItems) lie in tile h
+        const auto SW = real<R>(G.sw);
         uint64_t qh[kPtSplit] = {};
         uint32_t k[kPtItems];
-        float w[kPtItems];
+        R w[kPtItems];
 #pragma unroll
         for (int it = 0; it < kPtItems; ++it) {
             const uint32_t i = tile * kPtTile + it * kResThreads + threadIdx.x;
             k[it] = i < G.nu ? G.skey[i] : kNoCell;
-            w[it] = i < G.nu ? G.sw[i] : 0.0f;
+            w[it] = i < G.nu ? SW[i] : (R)0;
         }
         const bool assoc = static_cast<bool>(M.p_assoc);
 #pragma unroll
@@ -326,16 +389,16 @@ __global__ __launch_bounds__(kResThreads) void k_particle_tiles(Batch b)
             if (assoc && G.sum_wt[k[it]] > 0.0) {
                 const uint32_t c = k[it];
                 const double pa = (double)M.p_assoc[c];
-                const double g = likelihood((double)G.svx[i], (double)G.svy[i],
+                const double g = likelihood((double)real<R>(G.svx)[i], (double)real<R>(G.svy)[i],
                                             (double)M.mu_vx[c], (double)M.mu_vy[c],
                                             (double)M.var_v[c]);
                 wn = pa * G.mu_A[c] * (g * wd) + (1.0 - pa) * G.mu_UA[c] * wd;
             } else {
                 wn = G.mu_UA[k[it]] * wd;
             }
-            const float wf = (float)wn;
-            G.sw[i] = wf;
-            qh[it / kResItems] += fixed40(wf);
+            const R wr = (R)wn;
+            SW[i] = wr;
+            qh[it / kResItems] += fixed40(wr);
         }
 #pragma unroll
         for (int h = 0; h < kPtSplit; ++h) {
@@ -363,12 +426,13 @@ __global__ __launch_bounds__(kResThreads) void k_particle_tiles(Batch b)
         for (int w2 = 0; w2 < wave; ++w2) m = wave_last[w2] > m ? wave_last[w2] : m;
         if (s < G.nb) {
             if (Stot == 0) {  // no new-born mass anywhere: empty slots
-                G.bx[s] = G.by[s] = G.bvx[s] = G.bvy[s] = G.bw[s] = 0.0f;
+                real<R>(G.bx)[s] = real<R>(G.by)[s] = (R)0;
+                real<R>(G.bvx)[s] = real<R>(G.bvy)[s] = real<R>(G.bw)[s] = (R)0;
                 G.bkey[s] = G.C;
                 G.bassoc[s] = 0;
             } else {
                 const uint32_t c = (m != 0u && m - 1u > first) ? m - 1u : first;
-                q = fixed40(init_born(G, M, s, c, cycle));
+                q = fixed40(init_born<R>(G, M, s, c, cycle));
             }
         }
         const uint64_t qsum = block_sum(q, tmp);
@@ -383,7 +447,9 @@ hipError_t launch_particle_tiles(const GridRef* g, int n, hipStream_t s)
         make_batch(b, g, n, [](const GridDev& G) {
             return ceil_div(G.n_res_ptiles, kPtSplit) + G.n_born_parts;
         });
-    if (blocks) DOGM_LAUNCH(k_particle_tiles, dim3(blocks), dim3(kResThreads), 0, s, b);
+    if (blocks)
+        DOGM_LAUNCH_REAL(launch_real64(g, n), "k_particle_tiles", k_particle_tiles,
+                         dim3(blocks), dim3(kResThreads), 0, s, b);
     return hipGetLastError();
 }
 

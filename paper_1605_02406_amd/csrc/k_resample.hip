@@ -7,17 +7,19 @@
 // below W by more than the roundings of W, d and the product (1 - U >= 2^-24, so the margin is
 // at least 2^-24 / nu of W against three half-ulps), so every draw finds a particle.
 // Source i receives the draws J(F_{i-1}) <= j < J(F_i) with J(F) = min{ j : floor(u_j) >= F }.
-// One kernel: each tile adds up the totals of the tiles before it and scans its own weights
-// with wave prefix sums.  The draws of a wave's sources form one contiguous range; the wave
-// walks it in windows: every lane writes the local index of each of its sources into the
-// window's LDS map at the source's draws, then the wave writes the window's outputs in order,
-// so stores are coalesced and source reads ascend.
+// Each tile adds up the totals of the tiles before it (or, for grids with many tiles, reads
+// their prefix from a scan kernel) and scans its own weights with wave prefix sums.  The draws of a tile's sources form one contiguous range
+// of outputs; every source stores its first draw in LDS, and the block's threads then share
+// the tile's outputs evenly, each finding the source of an output by binary search among
+// those first draws.  A single source can receive a thousand draws or more (a new-born
+// particle alone in a cell with high new-born mass), so the outputs are not left to the lanes
+// that own the sources.  Consecutive outputs are written by consecutive lanes, and their sources ascend.
 #include "launch.h"
 
 namespace dogm {
 
 constexpr int kResWaves = kResThreads / kWave;
-constexpr int kResRounds = kResItems;  // each wave owns kResRounds * 64 consecutive items
+constexpr int kResRounds = kResItems;  // consecutive sources per lane
 static_assert(kResRounds % 4 == 0, "a lane reads its weights as 16-byte vectors");
 
 __device__ __forceinline__ uint64_t draw_floor(uint32_t j, double U, double spacing)
@@ -37,15 +39,12 @@ __device__ __forceinline__ uint32_t first_draw_at(uint64_t F, double U, double s
     return j;
 }
 
-constexpr int kResWindow = 1024;  // draws per LDS map window of a wave
-
-__global__ __launch_bounds__(kResThreads) void k_resample(Batch b)
+template <typename R>
+__global__ __launch_bounds__(kResThreads) void k_resample(Batch b, int prefixed)
 {
-    constexpr int kSrc = kResRounds * kWave;  // sources per wave
-    static_assert(kSrc <= 65536, "local source indices are 16-bit");
     __shared__ uint64_t tmp[kResWaves + 1];
     __shared__ uint64_t wave_tot[kResWaves];  // each wave's weight total
-    __shared__ uint16_t srcmap[kResWaves][kResWindow];
+    __shared__ uint32_t first[kResTile + 1];  // first draw of each source of the tile; the end
     const int gi = batch_grid(b);
     const GridView G = grid_view(b.g[gi]);
     const uint32_t ntiles = G.n_res_ptiles + G.n_res_btiles;
@@ -62,60 +61,53 @@ __global__ __launch_bounds__(kResThreads) void k_resample(Batch b)
     const bool born = tile >= G.n_res_ptiles;
     const uint32_t t_local = born ? tile - G.n_res_ptiles : tile;
     const uint32_t n_src = born ? G.nb : nu;
-    const uint32_t wbase = t_local * kResTile + wave * kSrc;
+    const uint32_t tbase = t_local * kResTile;
 
-    // each lane owns kResRounds consecutive sources; this wave's weights are read first so
-    // their loads overlap the prefix below
-    const uint32_t lbase = wbase + lane * kResRounds;
-    const auto wsrc = born ? G.bw : G.sw;
-    float wl[kResRounds];
+    // each lane owns kResRounds consecutive sources
+    const uint32_t lsrc = wave * (kResRounds * kWave) + lane * kResRounds;  // local index
+    const uint32_t lbase = tbase + lsrc;
+    const auto wsrc = real<R>(born ? G.bw : G.sw);
+    R wl[kResRounds];
     if (lbase + kResRounds <= n_src) {  // whole 16-byte vectors
+        using V = typename RealVec16<R>::type;
+        constexpr int kVec = 16 / (int)sizeof(R);
 #pragma unroll
-        for (int r = 0; r < kResRounds; r += 4) {
-            const f32x4 v = wsrc.load_vec<f32x4>(lbase + r);
+        for (int r = 0; r < kResRounds; r += kVec) {
+            const V v = wsrc.template load_vec<V>(lbase + r);
 #pragma unroll
-            for (int e = 0; e < 4; ++e) wl[r + e] = v[e];
+            for (int e = 0; e < kVec; ++e) wl[r + e] = v[e];
         }
     } else {
 #pragma unroll
         for (int r = 0; r < kResRounds; ++r) {
             const uint32_t i = lbase + r;
-            wl[r] = i < n_src ? wsrc[i] : 0.0f;
+            wl[r] = i < n_src ? wsrc[i] : (R)0;
         }
     }
 
     // joint weight before this tile and in total, from the partial sums of the persistent tiles
-    // (kResTile particles each) and of the new-born tiles (kBornTile slots each)
-    const uint32_t nparts = G.n_res_ptiles + G.n_born_parts;
+    // (kResTile particles each) and of the new-born tiles (kBornTile slots each), or from their
+    // exclusive prefixes where a scan has formed them
     const uint32_t limit = born ? G.n_res_ptiles + t_local * (kResTile / kBornTile) : tile;
-    uint64_t before = 0, all = 0;
-    for (uint32_t t0 = threadIdx.x; t0 < nparts; t0 += 4 * kResThreads) {
-        uint64_t v[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const uint32_t t = t0 + u * kResThreads;
-            v[u] = t < nparts ? G.rpart[t] : 0;
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            all += v[u];
-            if (t0 + u * kResThreads < limit) before += v[u];
-        }
+    uint64_t before, W;
+    if (prefixed) {
+        before = G.rpart[limit];
+        W = *G.W_fixed;
+    } else {
+        partials_before(G.rpart, G.n_res_ptiles + G.n_born_parts, limit, tmp, &before, &W);
+        if (tile == 0 && threadIdx.x == 0) *G.W_fixed = W;
     }
-    before = block_sum(before, tmp);
-    const uint64_t W = block_sum(all, tmp);
-    if (tile == 0 && threadIdx.x == 0) *G.W_fixed = W;
 
     if (W == 0) {  // nothing carries weight: keep the sorted persistent set as it is
         if (!born) {
             for (int r = 0; r < kResRounds; ++r) {
-                const uint32_t i = wbase + r * kWave + lane;
+                const uint32_t i = tbase + (uint32_t)(r * kResThreads) + threadIdx.x;
                 if (i < nu) {
-                    G.x[i] = G.sx[i];
-                    G.y[i] = G.sy[i];
-                    G.vx[i] = G.svx[i];
-                    G.vy[i] = G.svy[i];
-                    G.w[i] = G.sw[i];
+                    real<R>(G.x)[i] = real<R>(G.sx)[i];
+                    real<R>(G.y)[i] = real<R>(G.sy)[i];
+                    real<R>(G.vx)[i] = real<R>(G.svx)[i];
+                    real<R>(G.vy)[i] = real<R>(G.svy)[i];
+                    real<R>(G.w)[i] = real<R>(G.sw)[i];
                 }
             }
         }
@@ -134,86 +126,83 @@ __global__ __launch_bounds__(kResThreads) void k_resample(Batch b)
     __syncthreads();
     uint64_t run = before;
     for (int w2 = 0; w2 < wave; ++w2) run += wave_tot[w2];
-    const uint64_t wave_end = run + wave_tot[wave];
+    uint64_t tile_end = before;
+    for (int w2 = 0; w2 < kResWaves; ++w2) tile_end += wave_tot[w2];
 
     const double U = (double)unit_f32(draw(G, 0u, cycle, kPurposeResample).x);
     const double spacing = __ddiv_rn((double)W, (double)nu);
     const double inv_spacing = 1.0 / spacing;
-    const float out_w = (float)((double)W * 0x1p-40 / (double)nu);
+    const R out_w = (R)((double)W * 0x1p-40 / (double)nu);
 
-    // draws [j0, j1) of this lane's sources (local index lane * kResRounds + r); they tile the
-    // wave's range [j_begin, j_end) in source order
-    uint32_t j0[kResRounds], j1[kResRounds];
+    // first draw of each of this lane's sources; the draws of local source s are
+    // [first[s], first[s + 1]), and the tile's draws are [first[0], first[kResTile])
     uint64_t F = run + lincl - lsum;
 #pragma unroll
     for (int r = 0; r < kResRounds; ++r) {
-        j0[r] = first_draw_at(F, U, spacing, inv_spacing, nu);
+        first[lsrc + r] = first_draw_at(F, U, spacing, inv_spacing, nu);
         F += q[r];
     }
-    const uint32_t j_end = first_draw_at(wave_end, U, spacing, inv_spacing, nu);
-    const uint32_t next_lane = __shfl_down(j0[0], 1, kWave);
-#pragma unroll
-    for (int r = 0; r < kResRounds - 1; ++r) j1[r] = j0[r + 1];
-    j1[kResRounds - 1] = lane < kWave - 1 ? next_lane : j_end;
-    const uint32_t j_begin = __shfl(j0[0], 0, kWave);
+    if (threadIdx.x == 0) first[kResTile] = first_draw_at(tile_end, U, spacing, inv_spacing, nu);
+    __syncthreads();
+    const uint32_t j_begin = first[0], j_end = first[kResTile];
 
-    const auto px = born ? G.bx : G.sx;
-    const auto py = born ? G.by : G.sy;
-    const auto pvx = born ? G.bvx : G.svx;
-    const auto pvy = born ? G.bvy : G.svy;
-    uint16_t* map = srcmap[wave];
-    for (uint32_t wb = j_begin; wb < j_end; wb += kResWindow) {
-        const uint32_t we = min(wb + (uint32_t)kResWindow, j_end);
+    const auto px = real<R>(born ? G.bx : G.sx);
+    const auto py = real<R>(born ? G.by : G.sy);
+    const auto pvx = real<R>(born ? G.bvx : G.svx);
+    const auto pvy = real<R>(born ? G.bvy : G.svy);
+    const auto X = real<R>(G.x), Y = real<R>(G.y), VX = real<R>(G.vx), VY = real<R>(G.vy);
+    const auto Wt = real<R>(G.w);
+    // four outputs per thread per step, their source reads issued together; the source of
+    // output j is the last local source whose first draw is at or before j
+    constexpr int kUnroll = 4;
+    for (uint32_t j0 = j_begin + threadIdx.x; j0 < j_end; j0 += kUnroll * kResThreads) {
+        uint32_t src[kUnroll];
 #pragma unroll
-        for (int r = 0; r < kResRounds; ++r) {
-            const uint32_t lo = j0[r] > wb ? j0[r] : wb;
-            const uint32_t hi = j1[r] < we ? j1[r] : we;
-            for (uint32_t j = lo; j < hi; ++j) map[j - wb] = (uint16_t)(lane * kResRounds + r);
-        }
-        // the map is written and read by this wave only
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-        __builtin_amdgcn_wave_barrier();
-        // four outputs per lane per step, their source reads issued together
-        constexpr int kUnroll = 4;
-        for (uint32_t j0s = wb + lane; j0s < we; j0s += kUnroll * kWave) {
-            uint32_t src[kUnroll];
-            float ox[kUnroll], oy[kUnroll], ovx[kUnroll], ovy[kUnroll];
-#pragma unroll
-            for (int u = 0; u < kUnroll; ++u) {
-                const uint32_t j = j0s + u * kWave;
-                src[u] = j < we ? wbase + map[j - wb] : wbase;
-            }
-#pragma unroll
-            for (int u = 0; u < kUnroll; ++u) {
-                ox[u] = px[src[u]];
-                oy[u] = py[src[u]];
-                ovx[u] = pvx[src[u]];
-                ovy[u] = pvy[src[u]];
-            }
-#pragma unroll
-            for (int u = 0; u < kUnroll; ++u) {
-                const uint32_t j = j0s + u * kWave;
-                if (j < we) {
-                    G.x[j] = ox[u];
-                    G.y[j] = oy[u];
-                    G.vx[j] = ovx[u];
-                    G.vy[j] = ovy[u];
-                    G.w[j] = out_w;
+        for (int u = 0; u < kUnroll; ++u) {
+            const uint32_t j = j0 + u * kResThreads;
+            uint32_t lo = 0, hi = kResTile;  // first[lo] <= j < first[hi]
+            if (j < j_end) {
+                while (hi - lo > 1) {
+                    const uint32_t mid = (lo + hi) >> 1;
+                    if (first[mid] <= j) lo = mid;
+                    else hi = mid;
                 }
             }
+            src[u] = tbase + lo;
         }
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-        __builtin_amdgcn_wave_barrier();
+        R ox[kUnroll], oy[kUnroll], ovx[kUnroll], ovy[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            ox[u] = px[src[u]];
+            oy[u] = py[src[u]];
+            ovx[u] = pvx[src[u]];
+            ovy[u] = pvy[src[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            const uint32_t j = j0 + u * kResThreads;
+            if (j < j_end) {
+                X[j] = ox[u];
+                Y[j] = oy[u];
+                VX[j] = ovx[u];
+                VY[j] = ovy[u];
+                Wt[j] = out_w;
+            }
+        }
     }
 }
 
 hipError_t launch_resample(const GridRef* g, int n, hipStream_t s)
 {
+    bool prefixed = false;
+    if (const hipError_t e = launch_scan_parts(g, n, 1, &prefixed, s); e != hipSuccess) return e;
     Batch b;
     const uint32_t blocks = make_batch(b, g, n, [](const GridDev& G) {
         return xcd_blocks(G.n_res_ptiles + G.n_res_btiles);
     });
-    if (blocks) DOGM_LAUNCH(k_resample, dim3(blocks), dim3(kResThreads), 0, s, b);
+    if (blocks)
+        DOGM_LAUNCH_REAL(launch_real64(g, n), "k_resample", k_resample, dim3(blocks),
+                         dim3(kResThreads), 0, s, b, prefixed ? 1 : 0);
     return hipGetLastError();
 }
 

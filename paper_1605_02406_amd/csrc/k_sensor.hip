@@ -105,8 +105,11 @@ __global__ __launch_bounds__(kSensorThreads) void k_sensor_rays(const uint8_t* o
     const double inf = __builtin_huge_val();
     const double tdx = dx != 0.0 ? fabs(1.0 / dx) : inf;
     const double tdy = dy != 0.0 ? fabs(1.0 / dy) : inf;
-    double tmx = dx > 0.0 ? ((double)(ix + 1) - sx) / dx : (dx < 0.0 ? ((double)ix - sx) / dx : inf);
-    double tmy = dy > 0.0 ? ((double)(iy + 1) - sy) / dy : (dy < 0.0 ? ((double)iy - sy) / dy : inf);
+    // ray parameter of the first x and y cell boundaries, and their spacing
+    double tmx = dx > 0.0 ? ((double)(ix + 1) - sx) / dx
+                          : (dx < 0.0 ? ((double)ix - sx) / dx : inf);
+    double tmy = dy > 0.0 ? ((double)(iy + 1) - sy) / dy
+                          : (dy < 0.0 ? ((double)iy - sy) / dy : inf);
     for (int step = 0; step < 2 * (nx + ny); ++step) {
         const uint32_t c = (uint32_t)iy * (uint32_t)nx + (uint32_t)ix;
         seen[c] = 1;

@@ -292,6 +292,7 @@ constexpr int kGatherThreads = 256;
 constexpr int kGatherItems = 4;
 constexpr int kGatherTile = kGatherThreads * kGatherItems;
 
+template <typename R>
 __global__ __launch_bounds__(kGatherThreads) void k_gather(Batch b)
 {
     const int gi = batch_grid(b);
@@ -304,24 +305,24 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(Batch b)
         const uint32_t i = tile * kGatherTile + it * kGatherThreads + threadIdx.x;
         src[it] = i < G.nu ? G.perm[i] : 0u;
     }
-    float x[kGatherItems], y[kGatherItems], vx[kGatherItems], vy[kGatherItems], w[kGatherItems];
+    R x[kGatherItems], y[kGatherItems], vx[kGatherItems], vy[kGatherItems], w[kGatherItems];
 #pragma unroll
     for (int it = 0; it < kGatherItems; ++it) {
-        x[it] = G.x[src[it]];
-        y[it] = G.y[src[it]];
-        vx[it] = G.vx[src[it]];
-        vy[it] = G.vy[src[it]];
-        w[it] = G.w[src[it]];
+        x[it] = real<R>(G.x)[src[it]];
+        y[it] = real<R>(G.y)[src[it]];
+        vx[it] = real<R>(G.vx)[src[it]];
+        vy[it] = real<R>(G.vy)[src[it]];
+        w[it] = real<R>(G.w)[src[it]];
     }
 #pragma unroll
     for (int it = 0; it < kGatherItems; ++it) {
         const uint32_t i = tile * kGatherTile + it * kGatherThreads + threadIdx.x;
         if (i < G.nu) {
-            G.sx[i] = x[it];
-            G.sy[i] = y[it];
-            G.svx[i] = vx[it];
-            G.svy[i] = vy[it];
-            G.sw[i] = w[it];
+            real<R>(G.sx)[i] = x[it];
+            real<R>(G.sy)[i] = y[it];
+            real<R>(G.svx)[i] = vx[it];
+            real<R>(G.svy)[i] = vy[it];
+            real<R>(G.sw)[i] = w[it];
         }
     }
 }
@@ -381,7 +382,9 @@ hipError_t launch_sort(const GridRef* g, int n, hipStream_t s)
     const uint32_t gblocks = make_batch(b, g, n, [](const GridDev& G) {
         return xcd_blocks(ceil_div(G.nu, kGatherTile));
     });
-    if (gblocks) DOGM_LAUNCH(k_gather, dim3(gblocks), dim3(kGatherThreads), 0, s, b);
+    if (gblocks)
+        DOGM_LAUNCH_REAL(launch_real64(g, n), "k_gather", k_gather, dim3(gblocks),
+                         dim3(kGatherThreads), 0, s, b);
     // the particle range of every occupied cell, with the per-cell sums of the update
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? launch_cell_sums(g, n, s) : e;

@@ -34,12 +34,25 @@ inline void trace_after(const char* name, hipStream_t s)
     g_trace->n++;
 }
 
-// Every kernel launch of the library goes through this macro.
-#define DOGM_LAUNCH(kernel, grid, block, lds, stream, ...)                   \
+// Every kernel launch of the library goes through these macros; a kernel instantiated for the
+// precision mode is traced under its plain name.
+#define DOGM_LAUNCH_AS(name, kernel, grid, block, lds, stream, ...)          \
     do {                                                                     \
-        trace_before(#kernel, stream);                                       \
+        trace_before(name, stream);                                          \
         hipLaunchKernelGGL(kernel, grid, block, lds, stream, __VA_ARGS__);  \
-        trace_after(#kernel, stream);                                        \
+        trace_after(name, stream);                                           \
+    } while (0)
+#define DOGM_LAUNCH(kernel, grid, block, lds, stream, ...) \
+    DOGM_LAUNCH_AS(#kernel, kernel, grid, block, lds, stream, __VA_ARGS__)
+// The same kernel for the precision of the launch's grids (FP32 or FP64 real arrays).
+#define DOGM_LAUNCH_REAL(real64, name, kernel, grid, block, lds, stream, ...)                    \
+    do {                                                                                        \
+        if (real64)                                                                             \
+            DOGM_LAUNCH_AS(name, (kernel<double>), grid, block, lds, stream,      \
+                           __VA_ARGS__);                                                        \
+        else                                                                                    \
+            DOGM_LAUNCH_AS(name, (kernel<float>), grid, block, lds, stream,       \
+                           __VA_ARGS__);                                                        \
     } while (0)
 
 struct GridRef {
@@ -47,6 +60,9 @@ struct GridRef {
     const GridDev* dd;  // the descriptor in device memory
     MeasDev m;          // measurement of this cycle (update only)
 };
+
+// Precision of a launch: every grid of one launch has the same (the batched cycle groups them).
+inline bool launch_real64(const GridRef* g, int n) { return n > 0 && g[0].hd->real64 != 0; }
 
 // Fills b for grids g[0..n) with blocks_of(hd) blocks each; returns the total block count.
 template <typename F>
@@ -85,6 +101,11 @@ hipError_t launch_sort(const GridRef* g, int n, hipStream_t s);           // Alg
 hipError_t launch_cell_sums(const GridRef* g, int n, hipStream_t s);      // Alg. 2 ranges + sums
 hipError_t launch_update(const GridRef* g, int n, hipStream_t s);         // Alg. 3, 4, 5
 hipError_t launch_born_offsets(const GridRef* g, int n, hipStream_t s);   // Alg. 5 (slots)
+// Turns a launch's partial sums into exclusive prefixes when one of its grids has more than
+// kScanPartsFrom of them (which = 0: new-born masses, 1: joint weights); returns whether it did
+// in *prefixed.  Below that the consumers add up the partials before their own themselves.
+constexpr uint32_t kScanPartsFrom = 4096;
+hipError_t launch_scan_parts(const GridRef* g, int n, int which, bool* prefixed, hipStream_t s);
 hipError_t launch_particle_tiles(const GridRef* g, int n, hipStream_t s); // Alg. 4 + 5
 hipError_t launch_moments(const GridRef* g, int n, hipStream_t s);        // Alg. 6
 hipError_t launch_resample(const GridRef* g, int n, hipStream_t s);       // Alg. 7

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libdogm.so")
 DOGM_OK, DOGM_EINVAL, DOGM_ESIZE, DOGM_EHIP, DOGM_ESTATE, DOGM_ENOTIMPL = 0, -1, -2, -3, -4, -5
 ST_CONFLICT, ST_NOCARRIER, ST_NONFINITE, ST_INTERNAL = 1, 2, 4, 8
 MODEL_DS, MODEL_PHD_MIB = 0, 1  # Sec. VI (Dempster-Shafer), Sec. V (particle PHD/MIB)
+PRECISION_FP32, PRECISION_FP64 = 0, 1  # real-valued arrays in FP32, or everything in FP64
 
 # Names of the functions include/dogm.h declares.
 ABI = ["dogm_arena_bytes", "dogm_init_grid", "dogm_destroy", "dogm_set_stream", "dogm_set_cycle",
@@ -39,7 +40,7 @@ class CParams(ct.Structure):
                 ("sigma_pos", ct.c_float), ("sigma_vel", ct.c_float),
                 ("sigma_birth_vel", ct.c_float), ("alpha_free", ct.c_float),
                 ("n_pers", ct.c_int64), ("n_born", ct.c_int64), ("seed", ct.c_uint64),
-                ("grid_id", ct.c_uint32), ("model", ct.c_uint32)]
+                ("grid_id", ct.c_uint32), ("model", ct.c_uint32), ("precision", ct.c_uint32)]
 
 
 class CMeas(ct.Structure):
@@ -124,9 +125,9 @@ def _check(code: int, what: str):
 
 def make_params(nx, ny, cell_size, n_pers, n_born, dt=0.1, p_s=0.99, p_b=0.02, sigma_pos=0.1,
                 sigma_vel=0.5, sigma_birth_vel=4.0, alpha_free=0.9, seed=0, grid_id=0,
-                model=MODEL_DS) -> CParams:
+                model=MODEL_DS, precision=PRECISION_FP32) -> CParams:
     return CParams(nx, ny, cell_size, dt, p_s, p_b, sigma_pos, sigma_vel, sigma_birth_vel,
-                   alpha_free, n_pers, n_born, seed, grid_id, model)
+                   alpha_free, n_pers, n_born, seed, grid_id, model, precision)
 
 
 def arena_bytes(p: CParams) -> int:
@@ -174,7 +175,11 @@ class Grid:
         base = self.arena.data_ptr()
         sizes = {"nu": self.nu, "nb": self.nb, "C": self.C, "C1": self.C + 1, "1": 1}
         self.v = {}
+        real = torch.float64 if params.precision == PRECISION_FP64 else torch.float32
+        self.real = real
         for name, dt, kind in _VIEW_ARRAYS:
+            if dt == torch.float32:  # the real-valued arrays follow the precision mode
+                dt = real
             off = getattr(cv, name) - base
             n = sizes[kind]
             item = torch.empty((), dtype=dt).element_size()
@@ -243,7 +248,7 @@ class Grid:
     def load_state(self, st: dict):
         """Writes a host particle state (x, y, vx, vy, w) into the grid (stream-ordered)."""
         for k in ("x", "y", "vx", "vy", "w"):
-            self.v[k].copy_(torch.as_tensor(st[k], dtype=torch.float32), non_blocking=False)
+            self.v[k].copy_(torch.as_tensor(st[k], dtype=self.real), non_blocking=False)
 
 
 class KernelTrace:
