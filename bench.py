@@ -49,7 +49,8 @@ B_PER_CELL = 92
 CSRC = os.path.join(ROOT, "paper_1605_02406_amd", "csrc")
 KERNEL_SOURCE = {
     "k_predict": "k_particles.hip", "k_sort_hist": "k_sort.hip", "k_scan_rows": "k_sort.hip",
-    "k_sort_scatter": "k_sort.hip", "k_gather": "k_sort.hip", "k_seg_sums<false>": "k_cells.hip",
+    "k_sort_scatter": "k_sort.hip", "k_seg_sums<false>": "k_cells.hip", "k_scan_parts":
+    "k_particles.hip",
     "k_seg_sums<true>": "k_cells.hip", "k_cells<false>": "k_cells.hip",
     "k_cells<true>": "k_cells.hip", "k_seg_moments": "k_cells.hip",
     "k_born_offsets": "k_particles.hip", "k_particle_tiles": "k_particles.hip",
@@ -72,9 +73,7 @@ def sort_plan(C: int, max_bits: int = 11):
 def algorithmic_bytes(kernel: str, nu: int, nb: int, C: int) -> float:
     """Algorithmic bytes of ONE launch of `kernel` on one grid (averaged over the launches of a
     cycle where they differ), from per-unit figures: predict reads x, y, vx, vy, w (20 B) and
-    writes them and the key (24 B); a sort pass reads the key (and from the second pass on
-    the source index: 4 or 8 B) and writes key and index (8 B); the gather reads the
-    permutation and the predicted state (24 B) and writes the sorted state (20 B); the
+    writes them and the key (24 B); the
     resampling reads every joint weight (4 B), the state of each chosen source (16 B) and
     writes the 20-byte state of every output; the per-cell pass of the assignment reads the
     sorted key, weight and velocity (16 B per particle) and writes the cell range and six FP64
@@ -82,15 +81,16 @@ def algorithmic_bytes(kernel: str, nu: int, nb: int, C: int) -> float:
     writes masses, normalisers and moments (61 B) per cell; the slot offsets read rho_b and
     write o_c (8 B per cell); the tile pass rescales the persistent weights (key and weight
     read, weight written: 12 B per particle) and writes each new-born slot's 25-byte record.
-    (The cycle budget B_alg instead counts the whole assignment as one ideal pass over the
-    24-byte record: 48 B per particle.)"""
+    The sort counts as one ideal pass over the 24-byte record (read and written once: 48 B per
+    particle and cycle), shared evenly by its scatter launches; the scan of the partial sums
+    reads and writes one 8-byte sum per tile."""
     bits = sort_plan(C)
     if kernel == "k_predict":
         return 44.0 * nu
     if kernel == "k_sort_scatter":
-        return nu * sum((4.0 if q == 0 else 8.0) + 8.0 for q in range(len(bits))) / len(bits)
-    if kernel == "k_gather":
-        return 44.0 * nu
+        return 48.0 * nu / len(bits)
+    if kernel == "k_scan_parts":
+        return 16.0 * (-(-nu // 1024) + -(-nb // 256))
     if kernel == "k_sort_hist":
         return 4.0 * nu
     if kernel == "k_scan_rows":
@@ -241,11 +241,19 @@ def parse():
                          "until it is spent (0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one device copy of 1 GiB (for counter calibration)")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="use the library's default launch plan instead of the autotuner's")
+    ap.add_argument("--closed-loop-steps", type=int, default=50,
+                    help="timed cycles of the closed loop in which the device generates every "
+                         "measurement grid from the moving scene (0: skip)")
     ap.add_argument("--batch-steps", type=int, default=20,
                     help="timed cycles of the 16-grid batch (0: skip the batched mode)")
-    ap.add_argument("--serve-seconds", type=float, default=10.0,
+    ap.add_argument("--serve-seconds", type=float, default=60.0,
                     help="simulated seconds of the 64-stream serving replay (0: skip serving)")
-    ap.add_argument("--serve-speedups", default="1,10",
+    ap.add_argument("--serve-realtime-seconds", type=float, default=10.0,
+                    help="simulated seconds replayed at real time (speed 1), the rest of the "
+                         "speeds replay --serve-seconds")
+    ap.add_argument("--serve-speedups", default="1,10,30,100,300",
                     help="replay speeds of the serving run (1 = real time)")
     ap.add_argument("--serve-budget-gib", type=float, default=64.0,
                     help="HBM budget for admitting serving streams")
@@ -289,6 +297,12 @@ def main():
     t_gen = time.perf_counter() - t_gen
     dev = torch.device("cuda:0")
     meas = [dogm.Meas(**{k: torch.as_tensor(v, device=dev) for k, v in m.items()}) for m in seq]
+    plan, tuning = None, None
+    if not args.no_tune:
+        from paper_1605_02406_amd import tune
+        print("[bench] tuning the launch plan", file=sys.stderr, flush=True)
+        plan, tuning = tune.tune(p, meas=meas[:8])
+        p = tune.with_plan(p, plan)
     g = dogm.Grid(p)
     torch.cuda.synchronize()
 
@@ -355,6 +369,16 @@ def main():
     wall = time.perf_counter() - t0
     status = g.status()
     print("[bench] timed region done", file=sys.stderr, flush=True)
+    # new-born mass of the last cycle that fell on cells whose share of the nu_b slots rounds to
+    # none (no carrier): lost from the next cycle's state
+    rho_b = g.v["rho_b"].double()
+    off = g.v["born_off"].long()
+    no_slot = (rho_b > 0) & (off[1:] == off[:-1])
+    births_lost = {"cells_with_births": int((rho_b > 0).sum()),
+                   "cells_without_slot": int(no_slot.sum()),
+                   "mass_without_slot": float(rho_b[no_slot].sum()),
+                   "fraction_of_new_born_mass": float(rho_b[no_slot].sum() / max(float(rho_b.sum()),
+                                                                                   1e-300))}
 
     per_call = {n: float(np.mean([ev[s][i].elapsed_time(ev[s][i + 1]) for s in range(args.steps)]))
                 for i, n in enumerate(names)}
@@ -417,6 +441,8 @@ def main():
                      "traffic": traffic, "algorithmic_bytes_per_launch": dom_bytes,
                      "launch_ms_mean": dom_mean_ms, "launches_timed": len(dom_ms)},
         "status_word": status,
+        "launch_plan": {"plan": plan, "tuning_ms_per_cycle": tuning},
+        "births_without_slot": births_lost,
         "meas_generation_s": t_gen,
         # the assignment (radix sort and per-cell pass) against one ideal pass that reads and
         # writes a 24-byte record once: 8 TB/s / 48 B
@@ -429,14 +455,17 @@ def main():
         out["precision_study"] = study
 
     modes = {}
+    if args.closed_loop_steps > 0:
+        print("[bench] closed loop: device sensor + filter", file=sys.stderr, flush=True)
+        modes["closed_loop_device_sensor"] = bench_closed_loop(wl, p, args.closed_loop_steps)
     if args.batch_steps > 0:
         print("[bench] batched mode: 16 grids", file=sys.stderr, flush=True)
-        modes["batched_16_grids"] = bench_batched(args.batch_steps)
+        modes["batched_16_grids"] = bench_batched(args.batch_steps, tuned=not args.no_tune)
     if args.serve_seconds > 0:
         print("[bench] serving mode: 64 streams", file=sys.stderr, flush=True)
         modes["served_64_streams"] = bench_served(
             args.serve_seconds, [float(x) for x in args.serve_speedups.split(",") if x],
-            int(args.serve_budget_gib * (1 << 30)))
+            int(args.serve_budget_gib * (1 << 30)), realtime_seconds=args.serve_realtime_seconds)
     if modes:
         out["modes"] = modes
 
@@ -461,11 +490,69 @@ def b_alg(nu: int, nb: int, C: int) -> int:
     return B_PER_PARTICLE * nu + B_PER_BORN * nb + B_PER_CELL * C
 
 
-def bench_batched(steps: int, warmup: int = 5):
+def bench_closed_loop(wl: dict, p, steps: int, warmup: int = 5):
+    """The scene, the sensor and the filter in one loop on the device: per cycle the truth grid
+    of the moving scene (dogm_sensor_truth), the ray cast and detections (dogm_sensor_scan) and
+    the filter cycle, captured as one HIP graph per cycle and replayed.  Only the boxes'
+    rectangles come from the host, uploaded for every cycle before the timed region."""
+    import numpy as np
+    import torch
+
+    from paper_1605_02406_amd import dogm, scenes
+
+    dev = torch.device("cuda:0")
+    n = warmup + steps
+    sc = scenes.make_scene(wl, wl.get("seed", 0))
+    rects = []
+    for _ in range(n):
+        sc.advance()
+        rects.append(sc.rects())
+    rects = torch.as_tensor(np.stack(rects), dtype=torch.float64, device=dev)
+    static = torch.as_tensor(sc.static_mask().reshape(-1).astype(np.uint8), device=dev)
+    C = sc.nx * sc.ny
+    occ = torch.zeros(C, dtype=torch.uint8, device=dev)
+    seen = torch.zeros_like(occ)
+    m_occ = torch.zeros(C, dtype=torch.float32, device=dev)
+    m_free = torch.zeros_like(m_occ)
+    meas = dogm.Meas(m_occ, m_free)
+    g = dogm.Grid(p)
+
+    def cycle(k, stream=None):
+        dogm.sensor_truth(rects[k], static, sc.nx, sc.ny, sc.cell, occ, stream=stream)
+        dogm.sensor_scan(occ, sc.nx, sc.ny, scenes.SENSOR["p_d"], scenes.SENSOR["p_cl"], 4242,
+                         k + 1, seen, m_occ, m_free, stream=stream)
+        g.step(meas)
+
+    for k in range(warmup):
+        cycle(k)
+    side = torch.cuda.Stream()
+    graphs = []
+    for k in range(warmup, n):
+        gr = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(gr, stream=side):
+            cycle(k, stream=side)
+        graphs.append(gr)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for gr in graphs:
+        gr.replay()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    with dogm.KernelTrace(None, capacity=64) as tr:
+        cycle(warmup)  # one more eager cycle, traced, for the sensor's share
+    torch.cuda.synchronize()
+    sensor_ms = sum(d for nm, d in zip(tr.names(), tr.durations_ms()) if nm.startswith("k_sensor"))
+    return {"steps": steps, "ms_per_cycle": wall * 1e3 / steps, "cycles_per_s": steps / wall,
+            "sensor_kernels_ms_per_cycle": sensor_ms, "observed_cells_last_cycle":
+            int(seen.sum().item()), "status_word": g.status()}
+
+
+def bench_batched(steps: int, warmup: int = 5, tuned: bool = True):
     """16 grids of mixed sizes (4x128^2, 4x256^2, 3x384^2, 3x512^2, 2x768^2, 8 particles and one
     new-born slot per cell) stepped together, one launch per kernel for the whole batch, each
     batched cycle captured as a HIP graph and replayed; then the same grids stepped one after
-    another (the plain per-grid loop, 16 x 12 launches per cycle), captured and replayed alike."""
+    another (the plain per-grid loop), captured and replayed alike.  With `tuned`, every grid
+    shape's launch plan comes from the autotuner (the same plans in both modes)."""
     import numpy as np
     import torch
 
@@ -479,9 +566,16 @@ def bench_batched(steps: int, warmup: int = 5):
         seqs.append([dogm.Meas(torch.as_tensor(m["m_occ"], device=dev),
                                torch.as_tensor(m["m_free"], device=dev))
                      for m in scenes.measurement_sequence(wl, n_cycles)])
-    grids = [dogm.Grid(dogm.make_params(wl["nx"], wl["ny"], wl["cell"], wl["n_pers"],
-                                        wl["n_born"], seed=i, grid_id=i, **scenes.FILTER))
-             for i, wl in enumerate(wls)]
+    params = [dogm.make_params(wl["nx"], wl["ny"], wl["cell"], wl["n_pers"], wl["n_born"],
+                               seed=i, grid_id=i, **scenes.FILTER) for i, wl in enumerate(wls)]
+    plans = {}
+    if tuned:
+        from paper_1605_02406_amd import tune
+        for i, prm in enumerate(params):
+            plan, rep = tune.tune(prm)
+            plans[f'{prm.nx}x{prm.ny}'] = {"plan": plan, "tuning_ms_per_cycle": rep}
+            params[i] = tune.with_plan(prm, plan)
+    grids = [dogm.Grid(prm) for prm in params]
     for k in range(warmup):
         dogm.step_batch(grids, [sq[k] for sq in seqs])
     torch.cuda.synchronize()
@@ -531,16 +625,20 @@ def bench_batched(steps: int, warmup: int = 5):
             "per_grid_loop": {"ms_per_cycle": wall_l * 1e3 / steps,
                               "cycles_per_s": steps / wall_l,
                               "particles_per_s": nu * steps / wall_l},
-            "algorithmic_bytes_per_cycle": bytes_cycle, "status_words": status}
+            "algorithmic_bytes_per_cycle": bytes_cycle, "status_words": status,
+            "launch_plans": plans}
 
 
 def bench_served(seconds: float, speedups, budget: int, n_streams: int = 64, rate_hz: float = 10.0,
-                 pool: int = 4):
+                 pool: int = 4, realtime_seconds: float = 10.0):
     """64 streams of sizes drawn from {128^2, 256^2, 512^2} (8 particles and one new-born slot
     per cell), each receiving measurement grids as a Poisson process of `rate_hz` over `seconds`
     of simulated time, replayed at each speed in `speedups` through the serving runtime
-    (admission against `budget` bytes, continuous batching). Each stream cycles through `pool`
-    pre-uploaded measurement grids of its own scene."""
+    (admission against `budget` bytes, continuous batching); at speed 1 (real time) only the
+    first `realtime_seconds` are replayed, so the run holds the GPU for about that long.  The
+    speeds above the GPU's capacity show where serving saturates: the request rate stops
+    following the offered load and latency grows with the queue.  Each stream cycles through
+    `pool` pre-uploaded measurement grids of its own scene."""
     import numpy as np
     import torch
 
@@ -574,7 +672,8 @@ def bench_served(seconds: float, speedups, budget: int, n_streams: int = 64, rat
         srv.stats.done.clear()
         srv.stats.batches = srv.stats.batched_requests = 0
         count = {i: 1 for i in admitted}
-        todo = [(t, i) for t, i in arrivals if i in count]
+        horizon = min(seconds, realtime_seconds) if speed <= 1.0 else seconds
+        todo = [(t, i) for t, i in arrivals if i in count and t < horizon]
         clock = srv.clock
         t0 = clock()
         nxt = 0
@@ -588,13 +687,18 @@ def bench_served(seconds: float, speedups, budget: int, n_streams: int = 64, rat
             srv.pump()
         wall = clock() - t0
         lat = np.array([r.latency for r in srv.stats.done]) * 1e3
-        runs.append({"speedup": speed, "requests": int(lat.size), "wall_s": wall,
+        sizes_hist = {str(k): v for k, v in sorted(srv.stats.batch_sizes.items())}
+        runs.append({"speedup": speed, "simulated_s": horizon, "offered_requests_per_s":
+                     len(todo) / (horizon / speed), "requests": int(lat.size), "wall_s": wall,
                      "requests_per_s": lat.size / wall,
+                     "particles_per_s": sum(8 * int(srv.grids[r.sid].C) for r in srv.stats.done)
+                     / wall,
                      "latency_ms_p50": float(np.percentile(lat, 50)) if lat.size else None,
                      "latency_ms_p99": float(np.percentile(lat, 99)) if lat.size else None,
                      "latency_ms_max": float(lat.max()) if lat.size else None,
                      "batches": srv.stats.batches,
                      "mean_batch": srv.stats.batched_requests / max(srv.stats.batches, 1),
+                     "batch_sizes": sizes_hist,
                      "streams_admitted": len(admitted),
                      "streams_rejected": srv.stats.rejected_streams,
                      "hbm_reserved_bytes": srv.admission.used,

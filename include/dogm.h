@@ -74,7 +74,19 @@ typedef struct dogm_params {
     uint32_t grid_id;      /* fourth Philox counter word: separates grids with one seed     */
     uint32_t model;        /* DOGM_MODEL_DS (0) or DOGM_MODEL_PHD_MIB (1), see below        */
     uint32_t precision;    /* DOGM_PRECISION_FP32 (0) or DOGM_PRECISION_FP64 (1), see below */
+    /* Launch plan (results do not depend on it; a tuner picks it by timing, see below). */
+    uint32_t sort_passes;  /* radix passes of Alg. 2's sort: 0 = the fewest whose digits have
+                              at most 11 bits; else that many (at least the fewest, at most 3) */
+    uint32_t scan_parts;   /* prefix of the per-tile partial sums (new-born masses, joint
+                              weights): 0 = scanned once by a kernel of its own for grids with
+                              more than 4096 of them, else added up by every consumer block;
+                              1 = always scanned; 2 = scanned only when a grid of the same
+                              launch asks for it                                            */
 } dogm_params;
+
+/* The launch plan changes how the work is cut into launches and tiles, never a result: the sort
+ * is stable, so every digit plan gives the same permutation, and the prefix sums are exact
+ * integer sums whichever kernel forms them.  Grids with different plans may share a batch. */
 
 /* Precision modes.  DOGM_PRECISION_FP32: the particle state and the per-cell masses and moments
  * are stored in FP32; per-cell sums, the normalisation of Alg. 4 and the cell update are

@@ -61,6 +61,12 @@ bool valid_params(const dogm_params* p)
     if (p->n_born < 0 || p->n_born >= (int64_t(1) << 30)) return false;
     if (p->model != DOGM_MODEL_DS && p->model != DOGM_MODEL_PHD_MIB) return false;
     if (p->precision != DOGM_PRECISION_FP32 && p->precision != DOGM_PRECISION_FP64) return false;
+    // the plan: enough passes for the key bits with at most kSortBits per digit, at most 3
+    const int kb = key_bits((uint32_t)p->nx * (uint32_t)p->ny);
+    const uint32_t fewest = (uint32_t)((kb + kSortBits - 1) / kSortBits);
+    if (p->sort_passes != 0 && (p->sort_passes < fewest || p->sort_passes > kMaxPasses))
+        return false;
+    if (p->scan_parts > 2) return false;
     return true;
 }
 
@@ -135,6 +141,8 @@ GridDev describe(const dogm_params* p, char* base, size_t* bytes)
     // radix digits: as few passes of at most kSortBits bits as cover the largest key (C)
     const int kb = key_bits(C);
     d.passes = (uint32_t)((kb + kSortBits - 1) / kSortBits);
+    if (p->sort_passes > d.passes) d.passes = p->sort_passes;
+    d.scan_parts = p->scan_parts;
     uint32_t shift = 0;
     for (uint32_t q = 0; q < d.passes; ++q) {
         const uint32_t left = (uint32_t)kb - shift, passes_left = d.passes - q;
@@ -155,9 +163,10 @@ GridDev describe(const dogm_params* p, char* base, size_t* bytes)
     // real-valued arrays: FP32, or FP64 in the all-FP64 precision mode
     const size_t rb = d.real64 ? 8 : 4;
     const size_t r_nu = rb * nu, r_nb = rb * nb, r_c = rb * C;
-    float** pf_nu[] = {&d.x, &d.y, &d.vx, &d.vy, &d.w, &d.sx, &d.sy, &d.svx, &d.svy, &d.sw};
-    size_t o_pf_nu[10];
-    for (int i = 0; i < 10; ++i) o_pf_nu[i] = L.take(r_nu);
+    float** pf_nu[] = {&d.x, &d.y, &d.vx, &d.vy, &d.w, &d.sx, &d.sy, &d.svx, &d.svy, &d.sw,
+                       &d.tx, &d.ty, &d.tvx, &d.tvy, &d.tw};
+    size_t o_pf_nu[15];
+    for (int i = 0; i < 15; ++i) o_pf_nu[i] = L.take(r_nu);
     uint32_t** pu_nu[] = {&d.key, &d.skey, &d.perm, &d.tkey, &d.tval};
     size_t o_pu_nu[5];
     for (int i = 0; i < 5; ++i) o_pu_nu[i] = L.take(f_nu);
@@ -183,7 +192,7 @@ GridDev describe(const dogm_params* p, char* base, size_t* bytes)
     *bytes = L.total;
     if (!base) return d;
 
-    for (int i = 0; i < 10; ++i) *pf_nu[i] = at<float>(base, o_pf_nu[i]);
+    for (int i = 0; i < 15; ++i) *pf_nu[i] = at<float>(base, o_pf_nu[i]);
     for (int i = 0; i < 5; ++i) *pu_nu[i] = at<uint32_t>(base, o_pu_nu[i]);
     for (int i = 0; i < 2; ++i) *pu_c[i] = at<uint32_t>(base, o_pu_c[i]);
     for (int i = 0; i < 4; ++i) *pd_c[i] = at<double>(base, o_pd_c[i]);

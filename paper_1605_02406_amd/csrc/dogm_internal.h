@@ -126,6 +126,7 @@ struct GridT {
     uint32_t seed_lo, seed_hi, grid_id;
     uint32_t model;  // kModelPhdMib: Sec. V; otherwise the Dempster-Shafer model of Sec. VI
     uint32_t real64;  // 1: the real-valued arrays hold FP64 (all-FP64 precision mode), else FP32
+    uint32_t scan_parts;  // prefix of the partial sums: 0 automatic, 1 always scanned, 2 never
     // sort plan (from the largest key, C) and tilings
     uint32_t passes;
     uint32_t dshift[kMaxPasses], dbits[kMaxPasses];
@@ -136,7 +137,8 @@ struct GridT {
     // particles sorted by cell
     P<float> sx, sy, svx, svy, sw;
     P<uint32_t> skey, perm;
-    // ping-pong partner of the sorted keys and the permutation during the sort
+    // ping-pong partner of the sorted arrays during the sort
+    P<float> tx, ty, tvx, tvy, tw;
     P<uint32_t> tkey, tval;
     // cells
     P<uint32_t> cstart, cend;

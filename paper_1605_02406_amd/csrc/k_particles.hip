@@ -219,13 +219,13 @@ __global__ __launch_bounds__(kScanPartThreads) void k_scan_parts(Batch b, int wh
 
 hipError_t launch_scan_parts(const GridRef* g, int n, int which, bool* prefixed, hipStream_t s)
 {
-    uint32_t most = 0;
+    bool scan = false;
     for (int i = 0; i < n; ++i) {
         const GridDev& G = *g[i].hd;
         const uint32_t parts = which == 0 ? G.n_cell_parts : G.n_res_ptiles + G.n_born_parts;
-        most = parts > most ? parts : most;
+        scan |= G.scan_parts == 1 || (G.scan_parts == 0 && parts > kScanPartsFrom);
     }
-    *prefixed = most > kScanPartsFrom;
+    *prefixed = scan;
     if (!*prefixed) return hipSuccess;
     Batch b;
     const uint32_t blocks = make_batch(b, g, n, [](const GridDev&) { return 1u; });

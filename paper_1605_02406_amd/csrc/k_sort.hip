@@ -1,15 +1,17 @@
-// Alg. 2, first line: stable sort of the particles by cell key, and the particle state in sorted
-// order.
+// Alg. 2, first line: stable sort of the particles by cell key.
 //
-// LSD radix sort of (key, source index) pairs over digits of at most kSortBits bits (two passes
-// for grids up to 2^20 cells), then one gather of the predicted state into sorted order.  A pass
-// is three kernels that communicate only through memory: the digit histogram of every tile (for
-// the first pass it comes from the prediction kernel), a scan of each digit's row of tile counts,
-// and the scatter.  No block waits for another.  Only the 8-byte pairs travel through the
-// passes; the 20-byte state moves once, in the gather, whose reads follow the final order: after
-// resampling the particles are stored in cell order and one prediction moves them by a few
-// cells, so neighbouring sorted positions mostly read neighbouring sources.  The per-cell pass
-// that follows marks where each cell's run of sorted particles starts and ends.
+// LSD radix sort over digits of at most kSortBits bits (two passes for grids up to 2^20 cells);
+// each pass moves the key, the source index and the particle state (FP32, or FP64 in the all-FP64
+// precision mode).  A pass is three kernels that communicate only through memory: the digit
+// histogram of every tile (for the first pass it comes from the prediction kernel), a scan of
+// each digit's row of tile counts, and the scatter.  No block waits for another.  The per-cell
+// pass that follows marks where each cell's run of sorted particles starts and ends.
+//
+// The whole record travels with every pass, in runs of equal digits, so every read and write of
+// the state is coalesced.  (Moving only (key, index) pairs through the passes and the state
+// once, gathered in final order, measured no faster: position noise of half a cell spreads each
+// cell's particles over about nine cells, so the gather's reads touch two dozen cache lines per
+// wave and re-read three times the state through L2.)
 //
 // Stable ranking inside a tile: each of the block's 16 waves owns a contiguous sixteenth of the
 // tile (256 keys) and walks it 64 keys at a time; lanes holding the same digit find each other
@@ -26,17 +28,19 @@ namespace dogm {
 
 constexpr int kSortWaves = kSortThreads / kWave;
 
-// The pairs one pass reads and writes, as raw pointers (P = HostPtr) or global-space views.
+// The arrays one pass reads and writes, as raw pointers (P = HostPtr) or global-space views.
 template <template <typename> class P>
 struct SortArrays {
     P<uint32_t> ik;
     P<uint32_t> iv;  // null: the source index is the element index
+    P<float> ix, iy, ivx, ivy, iw;
     P<uint32_t> ok, ov;
+    P<float> ox, oy, ovx, ovy, ow;
 };
 
-// Pass p of P reads the predicted keys (p == 0) or the previous pass's pairs and writes the sorted
-// keys and the permutation on the last pass; the passes alternate between those and the
-// temporary pairs so that the last one lands in the sorted arrays.
+// Pass p of P reads the predicted state (p == 0) or the previous pass's output and writes the
+// sorted arrays on the last pass; the passes alternate between the sorted and the temporary
+// arrays so that the last one lands in the sorted arrays.
 template <template <typename> class P>
 __device__ __forceinline__ SortArrays<P> sort_arrays(const GridT<P>& G, uint32_t pass)
 {
@@ -44,15 +48,20 @@ __device__ __forceinline__ SortArrays<P> sort_arrays(const GridT<P>& G, uint32_t
     SortArrays<P> a;
     if (pass == 0) {
         a.ik = G.key; a.iv = P<uint32_t>{};
+        a.ix = G.x; a.iy = G.y; a.ivx = G.vx; a.ivy = G.vy; a.iw = G.w;
     } else if (dst_sorted) {
         a.ik = G.tkey; a.iv = G.tval;
+        a.ix = G.tx; a.iy = G.ty; a.ivx = G.tvx; a.ivy = G.tvy; a.iw = G.tw;
     } else {
         a.ik = G.skey; a.iv = G.perm;
+        a.ix = G.sx; a.iy = G.sy; a.ivx = G.svx; a.ivy = G.svy; a.iw = G.sw;
     }
     if (dst_sorted) {
         a.ok = G.skey; a.ov = G.perm;
+        a.ox = G.sx; a.oy = G.sy; a.ovx = G.svx; a.ovy = G.svy; a.ow = G.sw;
     } else {
         a.ok = G.tkey; a.ov = G.tval;
+        a.ox = G.tx; a.oy = G.ty; a.ovx = G.tvx; a.ovy = G.tvy; a.ow = G.tw;
     }
     return a;
 }
@@ -122,6 +131,20 @@ __global__ __launch_bounds__(kScanRowThreads) void k_scan_rows(Batch b, uint32_t
     if (threadIdx.x == 0) G.rowtot[d] = carry;
 }
 
+// Reads one state array for a wave's items (coalesced, zeros past the end); the array holds
+// the grid's real type R (its descriptor entry is typed FP32).
+template <typename R>
+__device__ __forceinline__ void load_items(const float* in, uint32_t base, uint32_t n,
+                                           R (&out)[kSortItems])
+{
+    const R* a = reinterpret_cast<const R*>(in);
+#pragma unroll
+    for (int it = 0; it < kSortItems; ++it) {
+        const uint32_t idx = base + it * kWave + lane_id();
+        out[it] = idx < n ? a[idx] : (R)0;
+    }
+}
+
 // Writes one payload array in destination order: every element goes to its local sorted slot in
 // LDS, then each thread moves the slots it owns to their global positions.
 template <typename T>
@@ -140,6 +163,7 @@ __device__ __forceinline__ void move_out(const T (&vals)[kSortItems], T* out, ui
         if (gpos[m] != 0xFFFFFFFFu) out[gpos[m]] = row[m * kSortThreads + threadIdx.x];
 }
 
+template <typename R>
 __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(Batch b, uint32_t pass)
 {
     extern __shared__ uint32_t lds[];
@@ -174,7 +198,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(Batch b, uint32_t
     const uint64_t lt_mask = (1ull << lane) - 1ull;
 
     // LDS: per-wave digit counts (16-bit: at most kSortTile per digit), local digit starts,
-    // global digit offsets, one staging row
+    // global digit offsets, one staging row (kSortTile values of the widest array moved)
     uint16_t* cnt = reinterpret_cast<uint16_t*>(lds);       // [kSortWaves][nbins]
     uint32_t* tstart = lds + (kSortWaves * nbins) / 2;      // [nbins]
     uint32_t* goff = tstart + nbins;                        // [nbins]
@@ -193,6 +217,9 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(Batch b, uint32_t
         k[it] = valid ? A.ik[idx] : 0u;
         v[it] = valid ? (A.iv ? A.iv[idx] : idx) : 0u;
     }
+    // the first state array is read while the tile is ranked
+    R pa[kSortItems], pb[kSortItems];
+    load_items(A.ix, base, G.nu, pa);
     // stable ranks inside the wave's quarter
 #pragma unroll
     for (int it = 0; it < kSortItems; ++it) {
@@ -280,55 +307,24 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(Batch b, uint32_t
             }
         }
     }
-    // the source index through the same LDS row
+    // the source index and the state, one array at a time through the same LDS row; the next
+    // array's loads are in flight while the current one is staged
     move_out(v, A.ov, stage, lpos, gpos);
+    load_items(A.iy, base, G.nu, pb);
+    move_out(pa, reinterpret_cast<R*>(A.ox), stage, lpos, gpos);
+    load_items(A.ivx, base, G.nu, pa);
+    move_out(pb, reinterpret_cast<R*>(A.oy), stage, lpos, gpos);
+    load_items(A.ivy, base, G.nu, pb);
+    move_out(pa, reinterpret_cast<R*>(A.ovx), stage, lpos, gpos);
+    load_items(A.iw, base, G.nu, pa);
+    move_out(pb, reinterpret_cast<R*>(A.ovy), stage, lpos, gpos);
+    move_out(pa, reinterpret_cast<R*>(A.ow), stage, lpos, gpos);
 }
 
-// The predicted state in sorted order: sorted position i takes particle perm[i].  Each thread
-// moves kGatherItems positions kGatherThreads apart, so a wave's reads of the permutation and its
-// writes are contiguous and its reads of the state follow the sources of 64 neighbouring sorted
-// positions.  Neighbouring tiles read neighbouring sources: each XCD walks one run of tiles.
-constexpr int kGatherThreads = 256;
-constexpr int kGatherItems = 4;
-constexpr int kGatherTile = kGatherThreads * kGatherItems;
-
-template <typename R>
-__global__ __launch_bounds__(kGatherThreads) void k_gather(Batch b)
-{
-    const int gi = batch_grid(b);
-    const GridView G = grid_view(b.g[gi]);
-    const uint32_t tile = xcd_tile(b, gi);
-    if (tile * kGatherTile >= G.nu) return;
-    uint32_t src[kGatherItems];
-#pragma unroll
-    for (int it = 0; it < kGatherItems; ++it) {
-        const uint32_t i = tile * kGatherTile + it * kGatherThreads + threadIdx.x;
-        src[it] = i < G.nu ? G.perm[i] : 0u;
-    }
-    R x[kGatherItems], y[kGatherItems], vx[kGatherItems], vy[kGatherItems], w[kGatherItems];
-#pragma unroll
-    for (int it = 0; it < kGatherItems; ++it) {
-        x[it] = real<R>(G.x)[src[it]];
-        y[it] = real<R>(G.y)[src[it]];
-        vx[it] = real<R>(G.vx)[src[it]];
-        vy[it] = real<R>(G.vy)[src[it]];
-        w[it] = real<R>(G.w)[src[it]];
-    }
-#pragma unroll
-    for (int it = 0; it < kGatherItems; ++it) {
-        const uint32_t i = tile * kGatherTile + it * kGatherThreads + threadIdx.x;
-        if (i < G.nu) {
-            real<R>(G.sx)[i] = x[it];
-            real<R>(G.sy)[i] = y[it];
-            real<R>(G.svx)[i] = vx[it];
-            real<R>(G.svy)[i] = vy[it];
-            real<R>(G.sw)[i] = w[it];
-        }
-    }
-}
-
-// The scatter's dynamic LDS (up to 96 KiB with 11-bit digits) is above the default limit: raise
-// it once on every device the library launches on (the attribute is per device).
+// The scatter's dynamic LDS (up to 112 KiB with 11-bit digits and FP64 state) is above the
+// default limit: raise it once on every device the library launches on (the attribute is per
+// device).
+constexpr int kScatterLdsMax = 112 * 1024;
 hipError_t allow_scatter_lds()
 {
     static std::mutex mu;
@@ -338,8 +334,11 @@ hipError_t allow_scatter_lds()
     if (e != hipSuccess) return e;
     std::lock_guard<std::mutex> lock(mu);
     if ((size_t)dev < done.size() && done[dev]) return hipSuccess;
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sort_scatter),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sort_scatter<float>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, kScatterLdsMax);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sort_scatter<double>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, kScatterLdsMax);
     if (e != hipSuccess) return e;
     if ((size_t)dev >= done.size()) done.resize(dev + 1, false);
     done[dev] = true;
@@ -374,17 +373,14 @@ hipError_t launch_sort(const GridRef* g, int n, hipStream_t s)
         const uint32_t tiles =
             make_batch(b, sub, m, [](const GridDev& G) { return xcd_blocks(G.n_sort_tiles); });
         const uint32_t nbins = 1u << maxbits;
+        const bool real64 = launch_real64(g, n);
         const size_t lds = sizeof(uint16_t) * (size_t)kSortWaves * nbins +
-                           sizeof(uint32_t) * (2 * (size_t)nbins + kSortTile);
-        if (tiles) DOGM_LAUNCH(k_sort_scatter, dim3(tiles), dim3(kSortThreads), lds, s, b, pass);
+                           sizeof(uint32_t) * 2 * (size_t)nbins +
+                           (real64 ? sizeof(double) : sizeof(uint32_t)) * kSortTile;
+        if (tiles)
+            DOGM_LAUNCH_REAL(real64, "k_sort_scatter", k_sort_scatter, dim3(tiles),
+                             dim3(kSortThreads), lds, s, b, pass);
     }
-    Batch b;
-    const uint32_t gblocks = make_batch(b, g, n, [](const GridDev& G) {
-        return xcd_blocks(ceil_div(G.nu, kGatherTile));
-    });
-    if (gblocks)
-        DOGM_LAUNCH_REAL(launch_real64(g, n), "k_gather", k_gather, dim3(gblocks),
-                         dim3(kGatherThreads), 0, s, b);
     // the particle range of every occupied cell, with the per-cell sums of the update
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? launch_cell_sums(g, n, s) : e;

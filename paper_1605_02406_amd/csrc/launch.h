@@ -101,9 +101,10 @@ hipError_t launch_sort(const GridRef* g, int n, hipStream_t s);           // Alg
 hipError_t launch_cell_sums(const GridRef* g, int n, hipStream_t s);      // Alg. 2 ranges + sums
 hipError_t launch_update(const GridRef* g, int n, hipStream_t s);         // Alg. 3, 4, 5
 hipError_t launch_born_offsets(const GridRef* g, int n, hipStream_t s);   // Alg. 5 (slots)
-// Turns a launch's partial sums into exclusive prefixes when one of its grids has more than
-// kScanPartsFrom of them (which = 0: new-born masses, 1: joint weights); returns whether it did
-// in *prefixed.  Below that the consumers add up the partials before their own themselves.
+// Turns a launch's partial sums into exclusive prefixes when one of its grids asks for it (its
+// plan says always, or automatic and it has more than kScanPartsFrom of them; which = 0:
+// new-born masses, 1: joint weights); returns whether it did in *prefixed.  Otherwise the
+// consumers add up the partials before their own themselves.
 constexpr uint32_t kScanPartsFrom = 4096;
 hipError_t launch_scan_parts(const GridRef* g, int n, int which, bool* prefixed, hipStream_t s);
 hipError_t launch_particle_tiles(const GridRef* g, int n, hipStream_t s); // Alg. 4 + 5

@@ -144,6 +144,7 @@ def evaluate(p_b: float, cycles: int = 80, warmup: int = 20, n_pers: int = 1 << 
     g = dogm.Grid(p)
     moving = [b for b in sc.boxes if b.vx != 0.0 or b.vy != 0.0]
     rows, scores, labels, counts, pigns = [], [], [], [], []
+    lost, born_total = 0.0, 0.0  # new-born mass on cells whose share of the slots rounds to none
     for k in range(1, cycles + 1):
         sc.advance()
         occ = sc.truth().reshape(-1)
@@ -157,6 +158,10 @@ def evaluate(p_b: float, cycles: int = 80, warmup: int = 20, n_pers: int = 1 << 
         g.step(meas)
         if k <= warmup:
             continue
+        rho_b = g.v["rho_b"].cpu().numpy().astype(np.float64)
+        off = g.v["born_off"].cpu().numpy().astype(np.int64)
+        lost += float(rho_b[(rho_b > 0) & (off[1:] == off[:-1])].sum())
+        born_total += float(rho_b.sum())
         mx = g.v["mean_x"].cpu().numpy()
         my = g.v["mean_y"].cpu().numpy()
         vxx = g.v["var_x"].cpu().numpy()
@@ -211,7 +216,8 @@ def evaluate(p_b: float, cycles: int = 80, warmup: int = 20, n_pers: int = 1 << 
             "roc_auc": auc(fpr, tpr),
             "tpr_at_fpr_1pct": tpr_at_fpr(fpr, tpr, 0.01),
             "roc_readings": roc_out,
-            "cells_dynamic": int(label.sum()), "cells_static": int((~label).sum())}
+            "cells_dynamic": int(label.sum()), "cells_static": int((~label).sum()),
+            "new_born_mass_without_slot_frac": lost / born_total if born_total > 0 else 0.0}
 
 
 def main():

@@ -89,6 +89,7 @@ class Stats:
     batches: int = 0
     batched_requests: int = 0
     rejected_streams: int = 0
+    batch_sizes: collections.Counter = field(default_factory=collections.Counter)  # size -> count
 
 
 class Server:
@@ -187,6 +188,7 @@ class Server:
         self.inflight.append(_Batch(ev, reqs, t))
         self.stats.batches += 1
         self.stats.batched_requests += len(reqs)
+        self.stats.batch_sizes[len(reqs)] += 1
         return len(reqs)
 
     def drain(self):

@@ -58,7 +58,8 @@ def test_arena_bytes_and_validation(dl):
     assert n2 > 8 * n
     bad = [dict(nx=0), dict(cell_size=0.0), dict(cell_size=float("nan")), dict(p_s=1.5),
            dict(p_b=-0.1), dict(alpha_free=2.0), dict(n_pers=0), dict(n_born=-1),
-           dict(n_pers=2 ** 27), dict(sigma_pos=-1.0), dict(nx=4096, ny=4096)]
+           dict(n_pers=2 ** 27), dict(sigma_pos=-1.0), dict(nx=4096, ny=4096),
+           dict(precision=2), dict(sort_passes=1), dict(sort_passes=4), dict(scan_parts=3)]
     for kw in bad:
         args = dict(nx=64, ny=64, cell_size=0.2, n_pers=32768, n_born=8192)
         args.update(kw)
@@ -66,6 +67,9 @@ def test_arena_bytes_and_validation(dl):
         with pytest.raises(dl.DogmError) as e:
             dl.arena_bytes(q)
         assert e.value.code == dl.DOGM_EINVAL
+    # launch plans: 64x64 keys need two passes of at most 11 bits; three are allowed
+    for sp in (0, 2, 3):
+        assert dl.arena_bytes(dl.make_params(64, 64, 0.2, 100, 10, sort_passes=sp)) > 0
     # the largest sizes the boundary accepts
     assert dl.arena_bytes(dl.make_params(4096, 4095, 0.2, 16, 0)) > 0
     assert dl.arena_bytes(dl.make_params(8, 8, 0.2, 2 ** 27 - 1, 0)) > 0

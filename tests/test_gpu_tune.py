@@ -1,0 +1,43 @@
+"""Launch plans (dogm_params.sort_passes, scan_parts) change no result: a grid stepped under
+every plan the autotuner considers is bit-identical to the default plan, and the tuner returns
+one of its candidates with a time for each."""
+import pytest
+import torch
+
+from paper_1605_02406_amd import dogm, scenes, tune
+from tests.parity import device_meas
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    dogm.lib()
+
+
+@pytest.mark.parametrize("n", [64, 256])
+def test_every_plan_gives_the_same_cycle(n):
+    wl = scenes.batch_workload(n, seed=2)
+    p = dogm.make_params(n, n, wl["cell"], wl["n_pers"], wl["n_born"], seed=4, **scenes.FILTER)
+    seq = [device_meas(m) for m in scenes.measurement_sequence(wl, 3)]
+    ref = dogm.Grid(p)
+    grids = [dogm.Grid(tune.with_plan(p, plan)) for plan in tune.candidates(p)]
+    assert len(grids) >= 2
+    for meas in seq:
+        ref.step(meas)
+        for g in grids:
+            g.step(meas)
+    torch.cuda.synchronize()
+    for g in grids:
+        for name, t in ref.v.items():
+            assert torch.equal(t, g.v[name]), name
+
+
+def test_tuner_picks_a_candidate():
+    wl = scenes.batch_workload(128, seed=1)
+    p = dogm.make_params(128, 128, wl["cell"], wl["n_pers"], wl["n_born"], **scenes.FILTER)
+    plan, report = tune.tune(p, warmup=2, cycles=3)
+    assert plan in tune.candidates(p)
+    assert len(report) == len(tune.candidates(p)) and all(v > 0 for v in report.values())
