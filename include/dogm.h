@@ -82,6 +82,10 @@ typedef struct dogm_params {
                               more than 4096 of them, else added up by every consumer block;
                               1 = always scanned; 2 = scanned only when a grid of the same
                               launch asks for it                                            */
+    uint32_t resample;     /* Alg. 7's outputs: 0 = automatic (1 above 2^22 persistent
+                              particles, else 2); 1 = every tile's outputs shared evenly by its
+                              threads; 2 = each source's draws written by the lane that owns it
+                              (one kernel per launch: 1 if any grid of the launch asks for it) */
 } dogm_params;
 
 /* The launch plan changes how the work is cut into launches and tiles, never a result: the sort

@@ -66,7 +66,7 @@ bool valid_params(const dogm_params* p)
     const uint32_t fewest = (uint32_t)((kb + kSortBits - 1) / kSortBits);
     if (p->sort_passes != 0 && (p->sort_passes < fewest || p->sort_passes > kMaxPasses))
         return false;
-    if (p->scan_parts > 2) return false;
+    if (p->scan_parts > 2 || p->resample > 2) return false;
     return true;
 }
 
@@ -143,6 +143,7 @@ GridDev describe(const dogm_params* p, char* base, size_t* bytes)
     d.passes = (uint32_t)((kb + kSortBits - 1) / kSortBits);
     if (p->sort_passes > d.passes) d.passes = p->sort_passes;
     d.scan_parts = p->scan_parts;
+    d.resample = p->resample;
     uint32_t shift = 0;
     for (uint32_t q = 0; q < d.passes; ++q) {
         const uint32_t left = (uint32_t)kb - shift, passes_left = d.passes - q;

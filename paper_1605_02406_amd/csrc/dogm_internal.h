@@ -127,6 +127,7 @@ struct GridT {
     uint32_t model;  // kModelPhdMib: Sec. V; otherwise the Dempster-Shafer model of Sec. VI
     uint32_t real64;  // 1: the real-valued arrays hold FP64 (all-FP64 precision mode), else FP32
     uint32_t scan_parts;  // prefix of the partial sums: 0 automatic, 1 always scanned, 2 never
+    uint32_t resample;    // resampling kernel: 0 automatic, 1 outputs shared evenly, 2 by owner
     // sort plan (from the largest key, C) and tilings
     uint32_t passes;
     uint32_t dshift[kMaxPasses], dbits[kMaxPasses];

@@ -19,6 +19,9 @@
 namespace dogm {
 
 constexpr int kResWaves = kResThreads / kWave;
+// the automatic plan shares outputs evenly (k_resample) above this many persistent particles and
+// lets the lanes that own the sources write their draws (k_resample_windowed) below it
+constexpr uint32_t kBalancedFrom = 1u << 22;
 constexpr int kResRounds = kResItems;  // consecutive sources per lane
 static_assert(kResRounds % 4 == 0, "a lane reads its weights as 16-byte vectors");
 
@@ -37,6 +40,45 @@ __device__ __forceinline__ uint32_t first_draw_at(uint64_t F, double U, double s
     while (j > 0 && draw_floor(j - 1, U, spacing) >= F) --j;
     while (j < nu && draw_floor(j, U, spacing) < F) ++j;
     return j;
+}
+
+// This lane's kResRounds consecutive source weights (16-byte vectors where whole).
+template <typename R>
+__device__ __forceinline__ void load_weights(const GArr<R>& wsrc, uint32_t lbase, uint32_t n_src,
+                                             R (&wl)[kResRounds])
+{
+    if (lbase + kResRounds <= n_src) {
+        using V = typename RealVec16<R>::type;
+        constexpr int kVec = 16 / (int)sizeof(R);
+#pragma unroll
+        for (int r = 0; r < kResRounds; r += kVec) {
+            const V v = wsrc.template load_vec<V>(lbase + r);
+#pragma unroll
+            for (int e = 0; e < kVec; ++e) wl[r + e] = v[e];
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < kResRounds; ++r) {
+            const uint32_t i = lbase + r;
+            wl[r] = i < n_src ? wsrc[i] : (R)0;
+        }
+    }
+}
+
+// Joint weight of the partial sums before `limit` (persistent tiles of kResTile particles, then
+// new-born tiles of kBornTile slots) and in total: from their exclusive prefixes where a scan
+// formed them, else added up by the block (tile 0 then stores the total).
+__device__ __forceinline__ void tile_prefix(const GridView& G, uint32_t limit, int prefixed,
+                                            uint32_t tile, uint64_t* tmp, uint64_t* before,
+                                            uint64_t* W)
+{
+    if (prefixed) {
+        *before = G.rpart[limit];
+        *W = *G.W_fixed;
+    } else {
+        partials_before(G.rpart, G.n_res_ptiles + G.n_born_parts, limit, tmp, before, W);
+        if (tile == 0 && threadIdx.x == 0) *G.W_fixed = *W;
+    }
 }
 
 template <typename R>
@@ -66,37 +108,13 @@ __global__ __launch_bounds__(kResThreads) void k_resample(Batch b, int prefixed)
     // each lane owns kResRounds consecutive sources
     const uint32_t lsrc = wave * (kResRounds * kWave) + lane * kResRounds;  // local index
     const uint32_t lbase = tbase + lsrc;
-    const auto wsrc = real<R>(born ? G.bw : G.sw);
     R wl[kResRounds];
-    if (lbase + kResRounds <= n_src) {  // whole 16-byte vectors
-        using V = typename RealVec16<R>::type;
-        constexpr int kVec = 16 / (int)sizeof(R);
-#pragma unroll
-        for (int r = 0; r < kResRounds; r += kVec) {
-            const V v = wsrc.template load_vec<V>(lbase + r);
-#pragma unroll
-            for (int e = 0; e < kVec; ++e) wl[r + e] = v[e];
-        }
-    } else {
-#pragma unroll
-        for (int r = 0; r < kResRounds; ++r) {
-            const uint32_t i = lbase + r;
-            wl[r] = i < n_src ? wsrc[i] : (R)0;
-        }
-    }
+    load_weights<R>(real<R>(born ? G.bw : G.sw), lbase, n_src, wl);
 
-    // joint weight before this tile and in total, from the partial sums of the persistent tiles
-    // (kResTile particles each) and of the new-born tiles (kBornTile slots each), or from their
-    // exclusive prefixes where a scan has formed them
+    // joint weight before this tile and in total
     const uint32_t limit = born ? G.n_res_ptiles + t_local * (kResTile / kBornTile) : tile;
     uint64_t before, W;
-    if (prefixed) {
-        before = G.rpart[limit];
-        W = *G.W_fixed;
-    } else {
-        partials_before(G.rpart, G.n_res_ptiles + G.n_born_parts, limit, tmp, &before, &W);
-        if (tile == 0 && threadIdx.x == 0) *G.W_fixed = W;
-    }
+    tile_prefix(G, limit, prefixed, tile, tmp, &before, &W);
 
     if (W == 0) {  // nothing carries weight: keep the sorted persistent set as it is
         if (!born) {
@@ -192,6 +210,152 @@ __global__ __launch_bounds__(kResThreads) void k_resample(Batch b, int prefixed)
     }
 }
 
+// The same draws written by the lanes that own the sources: each wave walks its own sources'
+// draws in windows of kResWindow, every lane writing the local index of each of its sources into
+// the window's LDS map at the source's draws, then the wave writes the window's outputs in order.
+// Cheaper per output than the binary search when sources receive few draws each; a source with
+// many draws is filled by its one lane.
+constexpr int kResWindow = 1024;  // draws per LDS map window of a wave
+
+template <typename R>
+__global__ __launch_bounds__(kResThreads) void k_resample_windowed(Batch b, int prefixed)
+{
+    constexpr int kSrc = kResRounds * kWave;  // sources per wave
+    static_assert(kSrc <= 65536, "local source indices are 16-bit");
+    __shared__ uint64_t tmp[kResWaves + 1];
+    __shared__ uint64_t wave_tot[kResWaves];  // each wave's weight total
+    __shared__ uint16_t srcmap[kResWaves][kResWindow];
+    const int gi = batch_grid(b);
+    const GridView G = grid_view(b.g[gi]);
+    const uint32_t ntiles = G.n_res_ptiles + G.n_res_btiles;
+    const uint32_t tile = xcd_tile(b, gi);
+    if (tile >= ntiles) return;
+    const uint32_t cycle = *G.cycle_run;
+    // the cycle ends here: every block stores the same next value of the counter that the
+    // prediction reads (no block of this kernel reads it)
+    if (threadIdx.x == 0) *G.cycle = cycle + 1u;
+    const uint32_t nu = G.nu;
+    const int lane = lane_id();
+    const int wave = threadIdx.x / kWave;
+
+    const bool born = tile >= G.n_res_ptiles;
+    const uint32_t t_local = born ? tile - G.n_res_ptiles : tile;
+    const uint32_t n_src = born ? G.nb : nu;
+    const uint32_t wbase = t_local * kResTile + wave * kSrc;
+
+    // each lane owns kResRounds consecutive sources
+    const uint32_t lbase = wbase + lane * kResRounds;
+    R wl[kResRounds];
+    load_weights<R>(real<R>(born ? G.bw : G.sw), lbase, n_src, wl);
+
+    // joint weight before this tile and in total
+    const uint32_t limit = born ? G.n_res_ptiles + t_local * (kResTile / kBornTile) : tile;
+    uint64_t before, W;
+    tile_prefix(G, limit, prefixed, tile, tmp, &before, &W);
+
+    if (W == 0) {  // nothing carries weight: keep the sorted persistent set as it is
+        if (!born) {
+            for (int r = 0; r < kResRounds; ++r) {
+                const uint32_t i = wbase + r * kWave + lane;
+                if (i < nu) {
+                    real<R>(G.x)[i] = real<R>(G.sx)[i];
+                    real<R>(G.y)[i] = real<R>(G.sy)[i];
+                    real<R>(G.vx)[i] = real<R>(G.svx)[i];
+                    real<R>(G.vy)[i] = real<R>(G.svy)[i];
+                    real<R>(G.w)[i] = real<R>(G.sw)[i];
+                }
+            }
+        }
+        return;
+    }
+
+    uint64_t q[kResRounds];
+    uint64_t lsum = 0;
+#pragma unroll
+    for (int r = 0; r < kResRounds; ++r) {
+        q[r] = fixed40(wl[r]);
+        lsum += q[r];
+    }
+    const uint64_t lincl = wave_incl_scan(lsum);
+    if (lane == kWave - 1) wave_tot[wave] = lincl;
+    __syncthreads();
+    uint64_t run = before;
+    for (int w2 = 0; w2 < wave; ++w2) run += wave_tot[w2];
+    const uint64_t wave_end = run + wave_tot[wave];
+
+    const double U = (double)unit_f32(draw(G, 0u, cycle, kPurposeResample).x);
+    const double spacing = __ddiv_rn((double)W, (double)nu);
+    const double inv_spacing = 1.0 / spacing;
+    const R out_w = (R)((double)W * 0x1p-40 / (double)nu);
+
+    // draws [j0, j1) of this lane's sources (local index lane * kResRounds + r); they tile the
+    // wave's range [j_begin, j_end) in source order
+    uint32_t j0[kResRounds], j1[kResRounds];
+    uint64_t F = run + lincl - lsum;
+#pragma unroll
+    for (int r = 0; r < kResRounds; ++r) {
+        j0[r] = first_draw_at(F, U, spacing, inv_spacing, nu);
+        F += q[r];
+    }
+    const uint32_t j_end = first_draw_at(wave_end, U, spacing, inv_spacing, nu);
+    const uint32_t next_lane = __shfl_down(j0[0], 1, kWave);
+#pragma unroll
+    for (int r = 0; r < kResRounds - 1; ++r) j1[r] = j0[r + 1];
+    j1[kResRounds - 1] = lane < kWave - 1 ? next_lane : j_end;
+    const uint32_t j_begin = __shfl(j0[0], 0, kWave);
+
+    const auto px = real<R>(born ? G.bx : G.sx);
+    const auto py = real<R>(born ? G.by : G.sy);
+    const auto pvx = real<R>(born ? G.bvx : G.svx);
+    const auto pvy = real<R>(born ? G.bvy : G.svy);
+    const auto X = real<R>(G.x), Y = real<R>(G.y), VX = real<R>(G.vx), VY = real<R>(G.vy);
+    const auto Wt = real<R>(G.w);
+    uint16_t* map = srcmap[wave];
+    for (uint32_t wb = j_begin; wb < j_end; wb += kResWindow) {
+        const uint32_t we = min(wb + (uint32_t)kResWindow, j_end);
+#pragma unroll
+        for (int r = 0; r < kResRounds; ++r) {
+            const uint32_t lo = j0[r] > wb ? j0[r] : wb;
+            const uint32_t hi = j1[r] < we ? j1[r] : we;
+            for (uint32_t j = lo; j < hi; ++j) map[j - wb] = (uint16_t)(lane * kResRounds + r);
+        }
+        // the map is written and read by this wave only
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        // four outputs per lane per step, their source reads issued together
+        constexpr int kUnroll = 4;
+        for (uint32_t j0s = wb + lane; j0s < we; j0s += kUnroll * kWave) {
+            uint32_t src[kUnroll];
+            R ox[kUnroll], oy[kUnroll], ovx[kUnroll], ovy[kUnroll];
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                const uint32_t j = j0s + u * kWave;
+                src[u] = j < we ? wbase + map[j - wb] : wbase;
+            }
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                ox[u] = px[src[u]];
+                oy[u] = py[src[u]];
+                ovx[u] = pvx[src[u]];
+                ovy[u] = pvy[src[u]];
+            }
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                const uint32_t j = j0s + u * kWave;
+                if (j < we) {
+                    X[j] = ox[u];
+                    Y[j] = oy[u];
+                    VX[j] = ovx[u];
+                    VY[j] = ovy[u];
+                    Wt[j] = out_w;
+                }
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
 hipError_t launch_resample(const GridRef* g, int n, hipStream_t s)
 {
     bool prefixed = false;
@@ -200,9 +364,22 @@ hipError_t launch_resample(const GridRef* g, int n, hipStream_t s)
     const uint32_t blocks = make_batch(b, g, n, [](const GridDev& G) {
         return xcd_blocks(G.n_res_ptiles + G.n_res_btiles);
     });
-    if (blocks)
-        DOGM_LAUNCH_REAL(launch_real64(g, n), "k_resample", k_resample, dim3(blocks),
-                         dim3(kResThreads), 0, s, b, prefixed ? 1 : 0);
+    if (blocks) {
+        // one kernel per launch (the results do not depend on it): the balanced one if any grid's
+        // plan asks for it
+        bool balanced = false;
+        for (int i = 0; i < n; ++i) {
+            const uint32_t mode = g[i].hd->resample;
+            balanced |= mode == 1 || (mode == 0 && g[i].hd->nu > kBalancedFrom);
+        }
+        const bool r64 = launch_real64(g, n);
+        if (balanced)
+            DOGM_LAUNCH_REAL(r64, "k_resample", k_resample, dim3(blocks), dim3(kResThreads), 0, s, b,
+                             prefixed ? 1 : 0);
+        else
+            DOGM_LAUNCH_REAL(r64, "k_resample", k_resample_windowed, dim3(blocks),
+                             dim3(kResThreads), 0, s, b, prefixed ? 1 : 0);
+    }
     return hipGetLastError();
 }
 

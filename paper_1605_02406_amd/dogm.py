@@ -41,7 +41,8 @@ class CParams(ct.Structure):
                 ("sigma_birth_vel", ct.c_float), ("alpha_free", ct.c_float),
                 ("n_pers", ct.c_int64), ("n_born", ct.c_int64), ("seed", ct.c_uint64),
                 ("grid_id", ct.c_uint32), ("model", ct.c_uint32), ("precision", ct.c_uint32),
-                ("sort_passes", ct.c_uint32), ("scan_parts", ct.c_uint32)]
+                ("sort_passes", ct.c_uint32), ("scan_parts", ct.c_uint32),
+                ("resample", ct.c_uint32)]
 
 
 class CMeas(ct.Structure):
@@ -127,10 +128,10 @@ def _check(code: int, what: str):
 def make_params(nx, ny, cell_size, n_pers, n_born, dt=0.1, p_s=0.99, p_b=0.02, sigma_pos=0.1,
                 sigma_vel=0.5, sigma_birth_vel=4.0, alpha_free=0.9, seed=0, grid_id=0,
                 model=MODEL_DS, precision=PRECISION_FP32, sort_passes=0,
-                scan_parts=0) -> CParams:
+                scan_parts=0, resample=0) -> CParams:
     return CParams(nx, ny, cell_size, dt, p_s, p_b, sigma_pos, sigma_vel, sigma_birth_vel,
                    alpha_free, n_pers, n_born, seed, grid_id, model, precision, sort_passes,
-                   scan_parts)
+                   scan_parts, resample)
 
 
 def arena_bytes(p: CParams) -> int:

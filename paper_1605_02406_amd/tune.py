@@ -6,7 +6,10 @@ stable and every prefix sum is exact), so the choice is a pure timing question:
   * sort_passes: the fewest radix passes with digits of at most 11 bits, or one more pass with
     narrower digits (smaller LDS per block, more blocks per compute unit, fewer ballots per key);
   * scan_parts: every consumer block adds up the per-tile partial sums before its own (no extra
-    launch), or one small kernel scans them once (an extra launch, one read per block).
+    launch), or one small kernel scans them once (an extra launch, one read per block);
+  * resample: every tile's outputs shared evenly by its threads (a binary search per output),
+    or each source's draws written by the lane that owns it (cheaper per output, but a source
+    with many draws is written by one lane).
 
     plan, report = tune(params)          # params: dogm.CParams
     params = with_plan(params, plan)
@@ -38,7 +41,8 @@ def candidates(params: dogm.CParams) -> list:
     C = params.nx * params.ny
     lo = fewest_passes(C)
     passes = [p for p in (lo, lo + 1) if p <= MAX_PASSES]
-    return [dict(sort_passes=p, scan_parts=s) for p, s in itertools.product(passes, (1, 2))]
+    return [dict(sort_passes=p, scan_parts=s, resample=r)
+            for p, s, r in itertools.product(passes, (1, 2), (1, 2))]
 
 
 def with_plan(params: dogm.CParams, plan: dict) -> dogm.CParams:
@@ -46,6 +50,7 @@ def with_plan(params: dogm.CParams, plan: dict) -> dogm.CParams:
     ct.pointer(q)[0] = params  # copy
     q.sort_passes = plan["sort_passes"]
     q.scan_parts = plan["scan_parts"]
+    q.resample = plan["resample"]
     return q
 
 
@@ -104,7 +109,8 @@ def tune(params: dogm.CParams, warmup: int = 4, cycles: int = 8, meas: list | No
     best, best_ms = None, float("inf")
     for plan in candidates(params):
         ms = time_plan(params, plan, meas, warmup, cycles)
-        report[f"passes={plan['sort_passes']},scan={plan['scan_parts']}"] = ms
+        report[f"passes={plan['sort_passes']},scan={plan['scan_parts']},"
+               f"resample={plan['resample']}"] = ms
         if ms < best_ms:
             best, best_ms = plan, ms
     _cache[key] = (best, report)

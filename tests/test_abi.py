@@ -59,7 +59,8 @@ def test_arena_bytes_and_validation(dl):
     bad = [dict(nx=0), dict(cell_size=0.0), dict(cell_size=float("nan")), dict(p_s=1.5),
            dict(p_b=-0.1), dict(alpha_free=2.0), dict(n_pers=0), dict(n_born=-1),
            dict(n_pers=2 ** 27), dict(sigma_pos=-1.0), dict(nx=4096, ny=4096),
-           dict(precision=2), dict(sort_passes=1), dict(sort_passes=4), dict(scan_parts=3)]
+           dict(precision=2), dict(sort_passes=1), dict(sort_passes=4), dict(scan_parts=3),
+           dict(resample=3)]
     for kw in bad:
         args = dict(nx=64, ny=64, cell_size=0.2, n_pers=32768, n_born=8192)
         args.update(kw)
