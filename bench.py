@@ -54,7 +54,7 @@ KERNEL_SOURCE = {
     "k_seg_sums<true>": "k_cells.hip", "k_cells<false>": "k_cells.hip",
     "k_cells<true>": "k_cells.hip", "k_seg_moments": "k_cells.hip",
     "k_born_offsets": "k_particles.hip", "k_particle_tiles": "k_particles.hip",
-    "k_resample": "k_resample.hip",
+    "k_resample": "k_resample.hip", "k_resample_windowed": "k_resample.hip",
 }
 
 
@@ -102,7 +102,7 @@ def algorithmic_bytes(kernel: str, nu: int, nb: int, C: int) -> float:
         return 16.0 * nu + 16.0 * C
     if kernel in ("k_cells<false>", "k_cells<true>"):
         return (68.0 + 61.0) * C
-    if kernel == "k_resample":
+    if kernel in ("k_resample", "k_resample_windowed"):
         return 4.0 * (nu + nb) + 16.0 * nu + 20.0 * nu
     if kernel == "k_particle_tiles":
         return 12.0 * nu + 25.0 * nb
@@ -243,6 +243,9 @@ def parse():
                     help="also run one device copy of 1 GiB (for counter calibration)")
     ap.add_argument("--no-tune", action="store_true",
                     help="use the library's default launch plan instead of the autotuner's")
+    ap.add_argument("--plan", default=None, metavar="P,S,R",
+                    help="fixed launch plan sort_passes,scan_parts,resample (no tuning); "
+                         "a profile of the tuned bench uses the plan the tuner printed")
     ap.add_argument("--closed-loop-steps", type=int, default=50,
                     help="timed cycles of the closed loop in which the device generates every "
                          "measurement grid from the moving scene (0: skip)")
@@ -298,7 +301,12 @@ def main():
     dev = torch.device("cuda:0")
     meas = [dogm.Meas(**{k: torch.as_tensor(v, device=dev) for k, v in m.items()}) for m in seq]
     plan, tuning = None, None
-    if not args.no_tune:
+    if args.plan:
+        from paper_1605_02406_amd import tune
+        ps, sp, rs = (int(x) for x in args.plan.split(","))
+        plan = dict(sort_passes=ps, scan_parts=sp, resample=rs)
+        p = tune.with_plan(p, plan)
+    elif not args.no_tune:
         from paper_1605_02406_amd import tune
         print("[bench] tuning the launch plan", file=sys.stderr, flush=True)
         plan, tuning = tune.tune(p, meas=meas[:8])

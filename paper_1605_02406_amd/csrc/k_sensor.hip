@@ -71,26 +71,44 @@ __global__ __launch_bounds__(kSensorThreads) void k_sensor_rays(const uint8_t* o
     extern __shared__ uint32_t bits[];
     const uint32_t C = (uint32_t)nx * (uint32_t)ny;
     if (kLds) {
-        // every block packs the whole occupancy grid into a bit mask, 32 cells per thread and
-        // step read as two 16-byte vectors where they are whole and aligned
+        // every block packs the whole occupancy grid into a bit mask, 32 cells per word read as
+        // two 16-byte vectors where they are whole and aligned; each thread issues the loads of
+        // kPackBatch words before packing them, so their latencies overlap
+        constexpr int kPackBatch = 8;
         const bool vec = (reinterpret_cast<uintptr_t>(occ) & 15u) == 0;
-        for (uint32_t wd = threadIdx.x; wd < (C + 31) / 32; wd += kSensorThreads) {
-            const uint32_t c0 = wd * 32;
-            uint32_t m = 0;
-            if (vec && c0 + 32 <= C) {
-                const uint4 a = reinterpret_cast<const uint4*>(occ + c0)[0];
-                const uint4 b = reinterpret_cast<const uint4*>(occ + c0)[1];
-                const uint32_t w8[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+        const uint32_t nwords = (C + 31) / 32;
+        for (uint32_t w0 = threadIdx.x; w0 < nwords; w0 += kPackBatch * kSensorThreads) {
+            uint4 va[kPackBatch], vb[kPackBatch];
 #pragma unroll
-                for (int q = 0; q < 8; ++q)
-#pragma unroll
-                    for (int e = 0; e < 4; ++e)
-                        if ((w8[q] >> (8 * e)) & 0xFFu) m |= 1u << (4 * q + e);
-            } else {
-                for (uint32_t b = 0; b < 32 && c0 + b < C; ++b)
-                    if (occ[c0 + b]) m |= 1u << b;
+            for (int q = 0; q < kPackBatch; ++q) {
+                const uint32_t c0 = (w0 + q * kSensorThreads) * 32;
+                if (vec && c0 + 32 <= C) {
+                    va[q] = reinterpret_cast<const uint4*>(occ + c0)[0];
+                    vb[q] = reinterpret_cast<const uint4*>(occ + c0)[1];
+                } else {
+                    va[q] = vb[q] = make_uint4(0u, 0u, 0u, 0u);
+                }
             }
-            bits[wd] = m;
+#pragma unroll
+            for (int q = 0; q < kPackBatch; ++q) {
+                const uint32_t wd = w0 + q * kSensorThreads;
+                if (wd >= nwords) break;
+                const uint32_t c0 = wd * 32;
+                uint32_t m = 0;
+                if (vec && c0 + 32 <= C) {
+                    const uint32_t w8[8] = {va[q].x, va[q].y, va[q].z, va[q].w,
+                                            vb[q].x, vb[q].y, vb[q].z, vb[q].w};
+#pragma unroll
+                    for (int k = 0; k < 8; ++k)
+#pragma unroll
+                        for (int e = 0; e < 4; ++e)
+                            if ((w8[k] >> (8 * e)) & 0xFFu) m |= 1u << (4 * k + e);
+                } else {
+                    for (uint32_t b = 0; b < 32 && c0 + b < C; ++b)
+                        if (occ[c0 + b]) m |= 1u << b;
+                }
+                bits[wd] = m;
+            }
         }
         __syncthreads();
     }
