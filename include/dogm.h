@@ -237,7 +237,8 @@ int dogm_update(dogm_grid* grid, const dogm_meas* meas);
  * updated persistent particles of every cell, normalised by rho_p; zeros and mom_flag 0
  * where rho_p <= 0 or the cell holds no particle.  Launches work only for a grid whose last
  * update had velocity evidence (otherwise the update already wrote the moments); the call is
- * still required in the order of a cycle. */
+ * still required in the order of a cycle.  It reads no measurement array: the buffers passed
+ * to the last dogm_update may be released once that call's work has completed. */
 int dogm_moments(dogm_grid* grid);
 
 /* Alg. 7, eq. (resampledParticleWeights): systematic resampling of nu particles from the joint

@@ -70,13 +70,20 @@ bool valid_params(const dogm_params* p)
     return true;
 }
 
+// Bytes left free after every array of the arena: none in the library; the CPU emulation of
+// the kernels (a test build) leaves a gap that it poisons, so an access past any array's end
+// is reported.
+#ifndef DOGM_ARENA_GAP
+#define DOGM_ARENA_GAP 0
+#endif
+
 // Offsets of every array inside the arena (the descriptor sits at offset 0).
 struct Layout {
     size_t total = 0;
     size_t take(size_t bytes)
     {
         const size_t o = (total + 255) & ~size_t(255);
-        total = o + (bytes ? bytes : 1);
+        total = o + (bytes ? bytes : 1) + DOGM_ARENA_GAP;
         return o;
     }
 };
@@ -246,8 +253,12 @@ hipError_t static_scratch(void** out)
 }
 
 // Velocity evidence (p_A > 0) is switched off: its kernels stay in the library but no entry
-// point launches them until a device fault seen with them is explained.
-bool evidence_enabled() { return false; }
+// point launches them until a device fault seen with them is explained.  The CPU emulation of
+// the kernels (a test build) compiles it in with DOGM_EVIDENCE=1.
+#ifndef DOGM_EVIDENCE
+#define DOGM_EVIDENCE 0
+#endif
+bool evidence_enabled() { return DOGM_EVIDENCE != 0; }
 
 int evidence_refused(const char* where)
 {
@@ -295,7 +306,9 @@ struct dogm_grid {
     uint32_t cycle;
     int phase;
     bool assoc;           // the last update had velocity evidence
-    dogm_meas last_meas;  // its measurement (the moments of that case read it)
+    // its measurement: dogm_moments passes it on only to mark the grid as one with evidence
+    // (the moments kernel reads no measurement array)
+    dogm_meas last_meas;
 
     GridRef ref(const dogm_meas* m = nullptr) const { return GridRef{&hd, dd, to_dev(m)}; }
 };

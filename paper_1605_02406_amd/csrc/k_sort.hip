@@ -235,6 +235,9 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(Batch b, uint32_t
         const uint32_t below = (uint32_t)__popcll(peers & lt_mask);
         uint32_t before = 0;
         if (valid) before = cnt[wave * nbins + d];
+        // every lane has read its digit's count before the lowest peer advances it (the wave
+        // runs in lockstep; the wave barrier states that order and costs no instruction)
+        __builtin_amdgcn_wave_barrier();
         if (valid && below == 0) cnt[wave * nbins + d] = (uint16_t)(before + (uint32_t)__popcll(peers));
         rank[it] = valid ? before + below : 0xFFFFFFFFu;
     }
