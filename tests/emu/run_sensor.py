@@ -1,0 +1,58 @@
+"""Test infrastructure: the device sensor (dogm_sensor_truth, dogm_sensor_scan) on the CPU
+emulation of the library, against the host scene generator (truth grid and observed cells
+bit-identical to Scene.truth() and scenes.raycast_observed).  Run with the AddressSanitizer
+runtime preloaded, as tests/emu/run_scene.py."""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import torch
+
+from paper_1605_02406_amd import dogm, scenes
+from tests.emu import build_emu
+from tests.emu.run_scene import HostStream
+
+SCENES = [("small", scenes.WORKLOADS["small"], 3),
+          ("c512", scenes.WORKLOADS["c512"], 1),
+          ("90x37", dict(nx=90, ny=37, cell=0.2, scene="boxes", n_boxes=6, clutter=0.02, seed=4), 3),
+          ("1x50", dict(nx=1, ny=50, cell=0.2, scene="boxes", n_boxes=1, clutter=0.1, seed=5), 2),
+          ("50x1", dict(nx=50, ny=1, cell=0.2, scene="boxes", n_boxes=1, clutter=0.1, seed=6), 2),
+          ("2x2", dict(nx=2, ny=2, cell=0.2, scene="boxes", n_boxes=0, clutter=0.0, seed=7), 1),
+          # beyond the LDS bit mask (1.32 M cells): the rays read the occupancy bytes
+          ("1200x1100", dict(nx=1200, ny=1100, cell=0.1, scene="boxes", n_boxes=40, clutter=0.002,
+                             seed=8), 1)]
+
+
+def main() -> int:
+    dogm.LIB_PATH = build_emu.LIB
+    s = HostStream()
+    for name, wl, cycles in SCENES:
+        sc = scenes.make_scene(wl, wl.get("seed", 0))
+        nx, ny = sc.nx, sc.ny
+        static = torch.as_tensor(sc.static_mask().reshape(-1).astype(np.uint8))
+        occ = torch.zeros(nx * ny, dtype=torch.uint8)
+        seen = torch.zeros_like(occ)
+        m_occ = torch.zeros(nx * ny, dtype=torch.float32)
+        m_free = torch.zeros_like(m_occ)
+        for k in range(1, cycles + 1):
+            sc.advance()
+            rects = torch.as_tensor(sc.rects(), dtype=torch.float64)
+            dogm.sensor_truth(rects, static, nx, ny, sc.cell, occ, stream=s)
+            dogm.sensor_scan(occ, nx, ny, 0.9, 0.01, 11, k, seen, m_occ, m_free, stream=s)
+            truth = sc.truth()
+            if not np.array_equal(occ.numpy().reshape(ny, nx) != 0, truth):
+                print(f"[emu] {name} cycle {k}: truth grid differs", flush=True)
+                return 1
+            ref = scenes.raycast_observed(truth)
+            got = seen.numpy().reshape(ny, nx) != 0
+            if not np.array_equal(got, ref):
+                print(f"[emu] {name} cycle {k}: observed cells differ in {int((got != ref).sum())}",
+                      flush=True)
+                return 1
+            print(f"[emu] {name} cycle {k}: {int(ref.sum())} observed cells equal", flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -57,3 +57,11 @@ def test_small_scene_without_evidence(emu_env):
 
 def test_all_fp64_with_velocity_evidence(emu_env):
     run(emu_env, "--workload", "small", "--cycles", "2", "--assoc", "--precision", "fp64")
+
+
+def test_device_sensor_equals_host_generator(emu_env):
+    r = subprocess.run([sys.executable, "-m", "tests.emu.run_sensor"], cwd=ROOT, env=emu_env,
+                       capture_output=True, text=True, timeout=900)
+    out = r.stdout + r.stderr
+    print(out[-3000:])
+    assert r.returncode == 0, out[-6000:]
