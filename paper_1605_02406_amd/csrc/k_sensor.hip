@@ -128,49 +128,19 @@ __global__ __launch_bounds__(kSensorThreads) void k_sensor_rays(const uint8_t* o
                           : (dx < 0.0 ? ((double)ix - sx) / dx : inf);
     double tmy = dy > 0.0 ? ((double)(iy + 1) - sy) / dy
                           : (dy < 0.0 ? ((double)iy - sy) / dy : inf);
-    // the traversal runs kAhead cells ahead of the occupancy tests: the cells of a batch come
-    // from the same sequence of boundary crossings (same arithmetic, same order), their
-    // occupancy reads are issued together, then the cells are marked in order up to the first
-    // occupied one; at most 2 (nx + ny) cells per ray
-    constexpr int kAhead = 8;
-    int left = 2 * (nx + ny);
-    for (;;) {
-        uint32_t cell[kAhead];
-        bool ok[kAhead];
-        bool going = true;  // the cell after the batch is still in the grid and not past the target
-#pragma unroll
-        for (int q = 0; q < kAhead; ++q) {
-            ok[q] = going && q < left;
-            cell[q] = (uint32_t)iy * (uint32_t)nx + (uint32_t)ix;
-            if (ok[q]) {
-                if (ix == px && iy == py) {
-                    going = false;
-                } else {
-                    if (tmx < tmy) {
-                        ix += stepx;
-                        tmx += tdx;
-                    } else {
-                        iy += stepy;
-                        tmy += tdy;
-                    }
-                    if (ix < 0 || ix >= nx || iy < 0 || iy >= ny) going = false;
-                }
-            }
+    for (int step = 0; step < 2 * (nx + ny); ++step) {
+        const uint32_t c = (uint32_t)iy * (uint32_t)nx + (uint32_t)ix;
+        seen[c] = 1;
+        const bool hit = kLds ? ((bits[c >> 5] >> (c & 31)) & 1u) != 0 : occ[c] != 0;
+        if (hit || (ix == px && iy == py)) break;
+        if (tmx < tmy) {
+            ix += stepx;
+            tmx += tdx;
+        } else {
+            iy += stepy;
+            tmy += tdy;
         }
-        uint32_t occw[kAhead];
-#pragma unroll
-        for (int q = 0; q < kAhead; ++q) {
-            if (kLds) occw[q] = ok[q] ? (bits[cell[q] >> 5] >> (cell[q] & 31)) & 1u : 0u;
-            else occw[q] = ok[q] ? (uint32_t)occ[cell[q]] : 0u;
-        }
-#pragma unroll
-        for (int q = 0; q < kAhead; ++q) {
-            if (!ok[q]) return;
-            seen[cell[q]] = 1;
-            if (occw[q] != 0) return;
-        }
-        left -= kAhead;
-        if (!going || left <= 0) return;
+        if (ix < 0 || ix >= nx || iy < 0 || iy >= ny) break;
     }
 }
 

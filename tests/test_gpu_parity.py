@@ -55,8 +55,8 @@ def test_small_scene_every_call_every_cycle():
 
 
 @pytest.mark.skip(reason="velocity evidence is switched off: its first GPU run ended in a device "
-                         "memory fault whose cause is not found yet (a CPU emulation of the same "
-                         "kernels runs this scene clean and exact)")
+                         "memory fault whose cause is not found yet (tests/test_emu.py runs the same "
+                         "kernels on this scene clean and exact under AddressSanitizer)")
 def test_small_scene_with_velocity_evidence():
     run_scene("small", 5, assoc=True)
 
