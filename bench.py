@@ -27,6 +27,7 @@ latency p50 / p99 at real time and at an accelerated replay).
 from __future__ import annotations
 
 import argparse
+import gc
 import hashlib
 import json
 import os
@@ -679,21 +680,31 @@ def bench_served(seconds: float, speedups, budget: int, n_streams: int = 64, rat
         srv.drain()
         srv.stats.done.clear()
         srv.stats.batches = srv.stats.batched_requests = 0
+        srv.stats.batch_sizes.clear()
         count = {i: 1 for i in admitted}
         horizon = min(seconds, realtime_seconds) if speed <= 1.0 else seconds
         todo = [(t, i) for t, i in arrivals if i in count and t < horizon]
         clock = srv.clock
-        t0 = clock()
-        nxt = 0
-        while nxt < len(todo) or srv.pending or srv.inflight:
-            now = clock()
-            while nxt < len(todo) and t0 + todo[nxt][0] / speed <= now:
-                t, i = todo[nxt]
-                srv.submit(i, meas[i][count[i] % pool], t_arrival=t0 + t / speed)
-                count[i] += 1
-                nxt += 1
-            srv.pump()
-        wall = clock() - t0
+        # the host loop runs with Python's cyclic garbage collector paused, as a serving loop
+        # would: a full collection walks the whole heap and stalls the loop for milliseconds
+        gc.collect()
+        gc.freeze()
+        gc.disable()
+        try:
+            t0 = clock()
+            nxt = 0
+            while nxt < len(todo) or srv.pending or srv.inflight:
+                now = clock()
+                while nxt < len(todo) and t0 + todo[nxt][0] / speed <= now:
+                    t, i = todo[nxt]
+                    srv.submit(i, meas[i][count[i] % pool], t_arrival=t0 + t / speed)
+                    count[i] += 1
+                    nxt += 1
+                srv.pump()
+            wall = clock() - t0
+        finally:
+            gc.enable()
+            gc.unfreeze()
         lat = np.array([r.latency for r in srv.stats.done]) * 1e3
         sizes_hist = {str(k): v for k, v in sorted(srv.stats.batch_sizes.items())}
         runs.append({"speedup": speed, "simulated_s": horizon, "offered_requests_per_s":

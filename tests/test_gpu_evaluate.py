@@ -49,3 +49,29 @@ def test_moving_cells_separate_from_static_ones(results):
         assert results[pb]["tpr_at_fpr_1pct"] > 0.9, pb
     # new-born particles blur the velocity of static cells: the separation is worst at high p_B
     assert results[0.1]["tpr_at_fpr_1pct"] < results[0.02]["tpr_at_fpr_1pct"]
+
+
+@pytest.fixture(scope="module")
+def approach():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    dogm.lib()
+    return {pb: evaluate.evaluate_approach(pb) for pb in (0.005, 0.1)}
+
+
+def test_constant_velocity_model_lags_the_manoeuvres(approach):
+    # an approaching object that accelerates, cruises and brakes (Sec. VIII.A): the estimate
+    # trails the truth while the object accelerates and overshoots it while it brakes
+    for pb, r in approach.items():
+        ph = r["phases"]
+        assert ph["accelerate"]["velocity_error_mean_mps"] < -0.5, pb
+        assert ph["decelerate"]["velocity_error_mean_mps"] > ph["accelerate"]["velocity_error_mean_mps"] + 0.8, pb
+    ph = approach[0.005]["phases"]
+    assert ph["decelerate"]["velocity_error_mean_mps"] > 0.1
+    assert abs(ph["stopped"]["velocity_error_mean_mps"]) < 0.3
+
+
+def test_births_bias_the_cruising_object_towards_zero(approach):
+    lo = approach[0.005]["phases"]["cruise"]["velocity_error_mean_mps"]
+    hi = approach[0.1]["phases"]["cruise"]["velocity_error_mean_mps"]
+    assert hi < lo - 0.3
