@@ -75,3 +75,37 @@ def test_births_bias_the_cruising_object_towards_zero(approach):
     lo = approach[0.005]["phases"]["cruise"]["velocity_error_mean_mps"]
     hi = approach[0.1]["phases"]["cruise"]["velocity_error_mean_mps"]
     assert hi < lo - 0.3
+
+
+@pytest.mark.parametrize("model", ["ds", "phd"])
+def test_lanes_scene_every_call_against_the_oracle(model):
+    """Per-call parity on the evaluation scene itself (320 x 160 cells, 2^19 + 2^16 particles):
+    two cycles stepped, then three cycles checked call by call."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import numpy as np
+
+    from paper_1605_02406_amd import scenes
+    from tests.parity import PerCall, device_meas
+
+    sc = evaluate.lanes_scene(seed=0)
+    p = dogm.make_params(sc.nx, sc.ny, sc.cell, 1 << 19, 1 << 16, seed=0,
+                         model=dogm.MODEL_PHD_MIB if model == "phd" else dogm.MODEL_DS,
+                         **scenes.FILTER)
+    g = dogm.Grid(p)
+    pc = PerCall(g)
+    for k in range(1, 6):
+        sc.advance()
+        occ = sc.truth()
+        rng = np.random.default_rng(np.random.SeedSequence([0, k, 99]))
+        if model == "phd":
+            m = scenes.detection_grid(occ, rng)
+        else:
+            m_occ, m_free = scenes.measurement_grid(occ, rng)
+            m = dict(m_occ=m_occ, m_free=m_free)
+        print(f"[lanes] {model} cycle {k}", flush=True)
+        if k <= 2:
+            g.step(device_meas(m))
+        else:
+            pc.cycle(device_meas(m))
+    assert g.status() & ~dogm.ST_NOCARRIER == 0
