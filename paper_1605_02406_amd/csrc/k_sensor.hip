@@ -20,7 +20,9 @@ namespace dogm {
 
 constexpr uint32_t kPurposeSensor = 4;
 constexpr int kSensorThreads = 256;
-constexpr uint32_t kRayLdsBits = 1u << 20;  // occupancy held as a bit mask in LDS up to 2^20 cells
+// the occupancy is held as a bit mask in LDS while the mask (rows padded to an odd number of
+// 32-bit words) takes at most this many bytes, else read from memory
+constexpr uint32_t kRayLdsMax = 160u * 1024u;
 
 __global__ __launch_bounds__(kSensorThreads) void k_sensor_truth(const double* rects, int n_rects,
                                                                  const uint8_t* static_occ,
@@ -70,19 +72,26 @@ __global__ __launch_bounds__(kSensorThreads) void k_sensor_rays(const uint8_t* o
 {
     extern __shared__ uint32_t bits[];
     const uint32_t C = (uint32_t)nx * (uint32_t)ny;
+    // LDS mask: row iy of the grid is words [iy * stride, iy * stride + ceil(nx / 32)), bit b of
+    // word w holding cell (32 w + b, iy); the row stride in words is odd, so the rays of a wave,
+    // which fan out across rows, read words in different LDS banks
+    const uint32_t row_words = ((uint32_t)nx + 31u) / 32u;
+    const uint32_t stride = row_words | 1u;
     if (kLds) {
-        // every block packs the whole occupancy grid into a bit mask, 32 cells per word read as
-        // two 16-byte vectors where they are whole and aligned; each thread issues the loads of
+        // every block packs the whole occupancy grid, each word from 32 bytes of one row (two
+        // 16-byte vectors where the row is whole and aligned); each thread issues the loads of
         // kPackBatch words before packing them, so their latencies overlap
         constexpr int kPackBatch = 8;
-        const bool vec = (reinterpret_cast<uintptr_t>(occ) & 15u) == 0;
-        const uint32_t nwords = (C + 31) / 32;
+        const bool vec = (reinterpret_cast<uintptr_t>(occ) & 15u) == 0 && nx % 16 == 0;
+        const uint32_t nwords = row_words * (uint32_t)ny;
         for (uint32_t w0 = threadIdx.x; w0 < nwords; w0 += kPackBatch * kSensorThreads) {
             uint4 va[kPackBatch], vb[kPackBatch];
 #pragma unroll
             for (int q = 0; q < kPackBatch; ++q) {
-                const uint32_t c0 = (w0 + q * kSensorThreads) * 32;
-                if (vec && c0 + 32 <= C) {
+                const uint32_t wd = w0 + q * kSensorThreads;
+                const uint32_t row = wd / row_words, x0 = (wd - row * row_words) * 32u;
+                const uint32_t c0 = row * (uint32_t)nx + x0;
+                if (vec && wd < nwords && x0 + 32 <= (uint32_t)nx) {
                     va[q] = reinterpret_cast<const uint4*>(occ + c0)[0];
                     vb[q] = reinterpret_cast<const uint4*>(occ + c0)[1];
                 } else {
@@ -93,9 +102,10 @@ __global__ __launch_bounds__(kSensorThreads) void k_sensor_rays(const uint8_t* o
             for (int q = 0; q < kPackBatch; ++q) {
                 const uint32_t wd = w0 + q * kSensorThreads;
                 if (wd >= nwords) break;
-                const uint32_t c0 = wd * 32;
+                const uint32_t row = wd / row_words, x0 = (wd - row * row_words) * 32u;
+                const uint32_t c0 = row * (uint32_t)nx + x0;
                 uint32_t m = 0;
-                if (vec && c0 + 32 <= C) {
+                if (vec && x0 + 32 <= (uint32_t)nx) {
                     const uint32_t w8[8] = {va[q].x, va[q].y, va[q].z, va[q].w,
                                             vb[q].x, vb[q].y, vb[q].z, vb[q].w};
 #pragma unroll
@@ -104,10 +114,10 @@ __global__ __launch_bounds__(kSensorThreads) void k_sensor_rays(const uint8_t* o
                         for (int e = 0; e < 4; ++e)
                             if ((w8[k] >> (8 * e)) & 0xFFu) m |= 1u << (4 * k + e);
                 } else {
-                    for (uint32_t b = 0; b < 32 && c0 + b < C; ++b)
+                    for (uint32_t b = 0; b < 32 && x0 + b < (uint32_t)nx; ++b)
                         if (occ[c0 + b]) m |= 1u << b;
                 }
-                bits[wd] = m;
+                bits[row * stride + (wd - row * row_words)] = m;
             }
         }
         __syncthreads();
@@ -128,19 +138,24 @@ __global__ __launch_bounds__(kSensorThreads) void k_sensor_rays(const uint8_t* o
                           : (dx < 0.0 ? ((double)ix - sx) / dx : inf);
     double tmy = dy > 0.0 ? ((double)(iy + 1) - sy) / dy
                           : (dy < 0.0 ? ((double)iy - sy) / dy : inf);
+    // one step per iteration with selects instead of branches: a wave runs one ray per lane, so
+    // the loop is bound by its instruction count, not by memory
     for (int step = 0; step < 2 * (nx + ny); ++step) {
         const uint32_t c = (uint32_t)iy * (uint32_t)nx + (uint32_t)ix;
         seen[c] = 1;
-        const bool hit = kLds ? ((bits[c >> 5] >> (c & 31)) & 1u) != 0 : occ[c] != 0;
-        if (hit || (ix == px && iy == py)) break;
-        if (tmx < tmy) {
-            ix += stepx;
-            tmx += tdx;
-        } else {
-            iy += stepy;
-            tmy += tdy;
-        }
-        if (ix < 0 || ix >= nx || iy < 0 || iy >= ny) break;
+        const bool hit = kLds ? ((bits[(uint32_t)iy * stride + ((uint32_t)ix >> 5)] >> (ix & 31)) & 1u) != 0
+                              : occ[c] != 0;
+        const bool xs = tmx < tmy;
+        const double tmx_n = tmx + tdx, tmy_n = tmy + tdy;
+        const int ixn = xs ? ix + stepx : ix, iyn = xs ? iy : iy + stepy;
+        tmx = xs ? tmx_n : tmx;
+        tmy = xs ? tmy : tmy_n;
+        // bitwise, not short-circuit: every term is one compare, none needs a branch
+        const bool stop = hit | ((ix == px) & (iy == py)) | (ixn < 0) | (ixn >= nx) | (iyn < 0) |
+                          (iyn >= ny);
+        if (stop) break;
+        ix = ixn;
+        iy = iyn;
     }
 }
 
@@ -174,7 +189,7 @@ hipError_t allow_ray_lds()
     std::lock_guard<std::mutex> lock(mu);
     if ((size_t)dev < done.size() && done[dev]) return hipSuccess;
     e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sensor_rays<true>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, kRayLdsBits / 8);
+                            hipFuncAttributeMaxDynamicSharedMemorySize, kRayLdsMax);
     if (e != hipSuccess) return e;
     if ((size_t)dev >= done.size()) done.resize(dev + 1, false);
     done[dev] = true;
@@ -200,9 +215,9 @@ hipError_t launch_sensor_scan(const uint8_t* occ, int nx, int ny, bool clear, do
     if (clear) DOGM_LAUNCH(k_sensor_clear, dim3(cblocks), dim3(kSensorThreads), 0, s, seen, C);
     const uint32_t n_rays = 2u * (uint32_t)nx + (ny >= 2 ? 2u * (uint32_t)(ny - 2) : 0u);
     const uint32_t rblocks = ceil_div(n_rays, kSensorThreads);
-    if (C <= kRayLdsBits) {
+    const size_t lds = 4ull * ((((uint32_t)nx + 31u) / 32u) | 1u) * (uint32_t)ny;
+    if (lds <= kRayLdsMax) {
         if (const hipError_t e = allow_ray_lds(); e != hipSuccess) return e;
-        const size_t lds = 4ull * ((C + 31) / 32);
         DOGM_LAUNCH(k_sensor_rays<true>, dim3(rblocks), dim3(kSensorThreads), lds, s, occ, nx, ny,
                     n_rays, seen);
     } else {
