@@ -159,6 +159,29 @@ def precision_study(path: str = os.path.join(PROFILES, "precision_c1024.json")):
                       for m in rec["modes"]}}
 
 
+def measured_copy_gbs(dev, nbytes: int = 1 << 30, reps: int = 10) -> float:
+    """Bandwidth of a plain device-to-device copy of `nbytes` (bytes read + bytes written per
+    second, median of `reps` event-timed copies): the practical HBM ceiling beside the vendor's
+    8 TB/s."""
+    import numpy as np
+    import torch
+
+    x = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+    y = torch.empty_like(x)
+    y.copy_(x)
+    times = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        y.copy_(x)
+        b.record()
+        b.synchronize()
+        times.append(a.elapsed_time(b) * 1e-3)
+    del x, y
+    torch.cuda.empty_cache()
+    return 2.0 * nbytes / float(np.median(times)) / 1e9
+
+
 def short_name(full: str) -> str:
     """Kernel name as the trace hook reports it, from the demangled name in a counter file."""
     name = full.split("(")[0].replace("void ", "").replace("dogm::", "").strip()
@@ -411,6 +434,9 @@ def main():
         y.copy_(x)
         torch.cuda.synchronize()
         del x, y
+    copy_gbs = measured_copy_gbs(dev)
+    # a copy whose 2 x 48 MB stay in the 256 MB last-level cache, the size of one cycle's arrays
+    copy_cached_gbs = measured_copy_gbs(dev, nbytes=48 << 20, reps=50)
 
     out = {
         "metric": METRIC,
@@ -444,11 +470,15 @@ def main():
         "cycle_roofline": {"bound": "hbm", "algorithmic_bytes": bytes_cycle,
                            "achieved": bytes_cycle / (ms_per_step * 1e-3) / 1e9,
                            "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": bytes_cycle / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS},
+                           "frac": bytes_cycle / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                           "frac_of_measured_copy":
+                               bytes_cycle / (ms_per_step * 1e-3) / 1e9 / copy_gbs},
         "roofline": {"kernel": dominant, "bound": "hbm", "achieved": dom_gbs,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": dom_gbs / HBM_PEAK_GBS,
                      "traffic": traffic, "algorithmic_bytes_per_launch": dom_bytes,
-                     "launch_ms_mean": dom_mean_ms, "launches_timed": len(dom_ms)},
+                     "launch_ms_mean": dom_mean_ms, "launches_timed": len(dom_ms),
+                     "measured_copy_GBps": copy_gbs, "frac_of_measured_copy": dom_gbs / copy_gbs,
+                     "measured_copy_cache_resident_GBps": copy_cached_gbs},
         "status_word": status,
         "launch_plan": {"plan": plan, "tuning_ms_per_cycle": tuning},
         "births_without_slot": births_lost,
