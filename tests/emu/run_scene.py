@@ -47,6 +47,8 @@ def main() -> int:
     ap.add_argument("--n-born", type=int, default=None)
     ap.add_argument("--assoc", action="store_true", help="with velocity evidence (p_A > 0)")
     ap.add_argument("--precision", choices=("fp32", "fp64"), default="fp32")
+    ap.add_argument("--model", choices=("ds", "phd"), default="ds",
+                    help="the Dempster-Shafer model of Sec. VI or the particle PHD/MIB model of Sec. V")
     args = ap.parse_args()
 
     dogm.LIB_PATH = build_emu.LIB  # the emulated build, loaded instead of the device library
@@ -70,7 +72,8 @@ def main() -> int:
     prec = dogm.PRECISION_FP64 if args.precision == "fp64" else dogm.PRECISION_FP32
     p = dogm.make_params(wl["nx"], wl["ny"], wl["cell"], args.n_pers or wl["n_pers"],
                          wl["n_born"] if args.n_born is None else args.n_born, seed=0,
-                         precision=prec, **f)
+                         precision=prec,
+                         model=dogm.MODEL_PHD_MIB if args.model == "phd" else dogm.MODEL_DS, **f)
     g = dogm.Grid(p, device="cpu", stream=HostStream())
     state = g.state
     g.state = lambda sorted_=False: {k: v.copy() for k, v in state(sorted_).items()}
@@ -80,7 +83,7 @@ def main() -> int:
         return 2
     print(f"[emu] {args.workload} nu={p.n_pers} nb={p.n_born} assoc={args.assoc} "
           f"{n} arena arrays guarded", flush=True)
-    seq = scenes.measurement_sequence(wl, args.cycles, with_truth=args.assoc)
+    seq = scenes.measurement_sequence(wl, args.cycles, with_truth=args.assoc, model=args.model)
     rng = np.random.default_rng(1)
     pc = PerCall(g)
     for k, m in enumerate(seq, start=1):

@@ -55,6 +55,10 @@ def test_small_scene_without_evidence(emu_env):
     run(emu_env, "--workload", "small", "--cycles", "2")
 
 
+def test_particle_phd_mib_model(emu_env):
+    run(emu_env, "--workload", "small", "--cycles", "2", "--model", "phd")
+
+
 def test_all_fp64_with_velocity_evidence(emu_env):
     run(emu_env, "--workload", "small", "--cycles", "2", "--assoc", "--precision", "fp64")
 
@@ -65,3 +69,12 @@ def test_device_sensor_equals_host_generator(emu_env):
     out = r.stdout + r.stderr
     print(out[-3000:])
     assert r.returncode == 0, out[-6000:]
+
+
+def test_batched_and_allocation_free_cycles_equal_the_single_cycle(emu_env):
+    r = subprocess.run([sys.executable, "-m", "tests.emu.run_modes"], cwd=ROOT, env=emu_env,
+                       capture_output=True, text=True, timeout=900)
+    out = r.stdout + r.stderr
+    print(out[-3000:])
+    assert r.returncode == 0, out[-6000:]
+    assert "shuffles reading an inactive lane 0" in out
