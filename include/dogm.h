@@ -46,7 +46,7 @@ enum {
     DOGM_ESIZE = -2,   /* arena too small                                          */
     DOGM_EHIP = -3,    /* a HIP call or kernel launch failed                       */
     DOGM_ESTATE = -4,  /* call out of order                                        */
-    DOGM_ENOTIMPL = -5 /* not available in this build                              */
+    DOGM_ENOTIMPL = -5 /* switched off in this version of the library             */
 };
 
 /* Device status word bits. */
@@ -127,8 +127,8 @@ enum { DOGM_MODEL_DS = 0, DOGM_MODEL_PHD_MIB = 1 };
  * NULL for p_A = 0 everywhere; when given, mu_vx, mu_vy, var_v (measured velocity and its
  * variance, > 0) define the spatial likelihood g(z|x) = N(v; mu, var I) and the associated
  * new-born velocity pdf, and must be non-NULL.
- * In this build velocity evidence is switched off: a non-NULL p_assoc makes dogm_update,
- * dogm_step and dogm_step_batch return DOGM_ENOTIMPL before anything is enqueued (the text
+ * Velocity evidence is switched off in this version: a non-NULL p_assoc makes dogm_update,
+ * dogm_step, dogm_step_noalloc and dogm_step_batch return DOGM_ENOTIMPL before anything is enqueued (the text
  * from dogm_status_string / dogm_last_error says so).
  * For a grid of DOGM_MODEL_PHD_MIB (Sec. V.C observation process) p_tp, p_fp and det are
  * required instead of m_occ, m_free (which are not read) and p_assoc must be NULL: p_tp, p_fp

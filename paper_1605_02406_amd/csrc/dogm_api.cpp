@@ -262,7 +262,7 @@ bool evidence_enabled() { return DOGM_EVIDENCE != 0; }
 
 int evidence_refused(const char* where)
 {
-    g_last_error = std::string(where) + ": velocity evidence (p_assoc) is disabled in this build";
+    g_last_error = std::string(where) + ": velocity evidence (p_assoc) is disabled in this version of the library";
     return DOGM_ENOTIMPL;
 }
 
