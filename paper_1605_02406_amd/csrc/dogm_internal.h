@@ -359,6 +359,15 @@ __device__ __forceinline__ uint64_t fixed40(float m) { return fixed40((double)m)
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
 
+// a * b + c rounded twice, as written: where an integer decision depends on the value and the
+// other side of a comparison computes it the same way, it must not become a fused multiply-add
+// (device code contracts a * b + c by default).
+__device__ __forceinline__ double mul_add_twice_rounded(double a, double b, double c)
+{
+#pragma clang fp contract(off)
+    return a * b + c;
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_incl_scan(T v)
 {

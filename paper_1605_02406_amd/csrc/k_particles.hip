@@ -326,7 +326,7 @@ __device__ __forceinline__ R init_born(const GridView& G, const MeasView& M, uin
     const uint32_t o0 = G.born_off[c], o1 = G.born_off[c + 1];
     const uint32_t n_c = o1 - o0;
     const double pa = M.p_assoc ? (double)M.p_assoc[c] : 0.0;
-    const uint32_t na = (uint32_t)floor(__dadd_rn(__dmul_rn(pa, (double)n_c), 0.5));
+    const uint32_t na = (uint32_t)floor(mul_add_twice_rounded(pa, (double)n_c, 0.5));
     const uint32_t nua = n_c - na;
     const bool assoc = (s - o0) < na;
     const double rb = (double)real<R>(G.rho_b)[c];

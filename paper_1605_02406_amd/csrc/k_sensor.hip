@@ -6,23 +6,19 @@
 //    (boxes and walls, bounds included) or in the static occupancy mask (clutter);
 //  - rays: one Amanatides-Woo traversal per perimeter cell, from the sensor at the grid centre
 //    towards that cell's centre, marking every cell it passes up to and including the first
-//    occupied one (or the perimeter cell); all arithmetic in FP64, in the order of the
-//    traversal's definition, so the cells marked do not depend on the device;
+//    occupied one (or the perimeter cell); the i-th boundary crossing along an axis is at
+//    t_i = t_0 + i d (FP64, one rounded product and one rounded sum), so any step of the walk
+//    can be formed on its own and a wave walks one ray 64 cells at a time;
 //  - detect: in every observed cell one Bernoulli draw from Philox4x32-10 (counter: cell, cycle,
 //    purpose 4, 0): probability p_D where occupied, the clutter probability p_cl where free; the
 //    evidence masses are (m_O, 0) for a detection and (0, m_F) for an observed cell without one.
-#include <mutex>
-#include <vector>
-
 #include "launch.h"
 
 namespace dogm {
 
 constexpr uint32_t kPurposeSensor = 4;
 constexpr int kSensorThreads = 256;
-// the occupancy is held as a bit mask in LDS while the mask (rows padded to an odd number of
-// 32-bit words) takes at most this many bytes, else read from memory
-constexpr uint32_t kRayLdsMax = 160u * 1024u;
+constexpr int kRaysPerBlock = kSensorThreads / kWave;  // one ray per wave
 
 __global__ __launch_bounds__(kSensorThreads) void k_sensor_truth(const double* rects, int n_rects,
                                                                  const uint8_t* static_occ,
@@ -65,97 +61,67 @@ __device__ __forceinline__ void ray_target(uint32_t k, int nx, int ny, int& px, 
     py = (int)(k - side) + 1;
 }
 
-template <bool kLds>
+// Ray parameter of the i-th cell boundary crossed along one axis: t_0 is the first crossing,
+// t_i = t_0 + i d after it (d = 1 / |direction|; infinite for an axis the ray does not move
+// along, where every crossing is infinite).
+__device__ __forceinline__ double crossing(double t0, double d, uint32_t i)
+{
+    return i == 0 ? t0 : mul_add_twice_rounded((double)i, d, t0);
+}
+
+// Steps along x among the first n steps of a ray.  Each step crosses the nearer boundary, an x
+// boundary only when its crossing is strictly smaller, so the steps merge the two increasing
+// sequences of crossings (ties to y), and after n steps the number of x steps is the largest i
+// in [0, n] with i = 0 or X(i - 1) < Y(n - i): the predicate holds up to it and fails after it.
+__device__ __forceinline__ uint32_t x_steps(uint32_t n, double tmx, double tdx, double tmy,
+                                            double tdy)
+{
+    uint32_t lo = 0, hi = n;
+    while (lo < hi) {
+        const uint32_t mid = lo + (hi - lo + 1) / 2;
+        if (crossing(tmx, tdx, mid - 1) < crossing(tmy, tdy, n - mid)) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// One ray per wave: each lane forms one cell of the walk (step base + lane), and one ballot
+// finds the first lane whose cell ends the ray (occupied, the target cell, outside the grid, or
+// past the step limit of 2 (nx + ny)); the lanes up to it mark their cells.
 __global__ __launch_bounds__(kSensorThreads) void k_sensor_rays(const uint8_t* occ, int nx,
                                                                 int ny, uint32_t n_rays,
                                                                 uint8_t* seen)
 {
-    extern __shared__ uint32_t bits[];
-    const uint32_t C = (uint32_t)nx * (uint32_t)ny;
-    // LDS mask: row iy of the grid is words [iy * stride, iy * stride + ceil(nx / 32)), bit b of
-    // word w holding cell (32 w + b, iy); the row stride in words is odd, so the rays of a wave,
-    // which fan out across rows, read words in different LDS banks
-    const uint32_t row_words = ((uint32_t)nx + 31u) / 32u;
-    const uint32_t stride = row_words | 1u;
-    if (kLds) {
-        // every block packs the whole occupancy grid, each word from 32 bytes of one row (two
-        // 16-byte vectors where the row is whole and aligned); each thread issues the loads of
-        // kPackBatch words before packing them, so their latencies overlap
-        constexpr int kPackBatch = 8;
-        const bool vec = (reinterpret_cast<uintptr_t>(occ) & 15u) == 0 && nx % 16 == 0;
-        const uint32_t nwords = row_words * (uint32_t)ny;
-        for (uint32_t w0 = threadIdx.x; w0 < nwords; w0 += kPackBatch * kSensorThreads) {
-            uint4 va[kPackBatch], vb[kPackBatch];
-#pragma unroll
-            for (int q = 0; q < kPackBatch; ++q) {
-                const uint32_t wd = w0 + q * kSensorThreads;
-                const uint32_t row = wd / row_words, x0 = (wd - row * row_words) * 32u;
-                const uint32_t c0 = row * (uint32_t)nx + x0;
-                if (vec && wd < nwords && x0 + 32 <= (uint32_t)nx) {
-                    va[q] = reinterpret_cast<const uint4*>(occ + c0)[0];
-                    vb[q] = reinterpret_cast<const uint4*>(occ + c0)[1];
-                } else {
-                    va[q] = vb[q] = make_uint4(0u, 0u, 0u, 0u);
-                }
-            }
-#pragma unroll
-            for (int q = 0; q < kPackBatch; ++q) {
-                const uint32_t wd = w0 + q * kSensorThreads;
-                if (wd >= nwords) break;
-                const uint32_t row = wd / row_words, x0 = (wd - row * row_words) * 32u;
-                const uint32_t c0 = row * (uint32_t)nx + x0;
-                uint32_t m = 0;
-                if (vec && x0 + 32 <= (uint32_t)nx) {
-                    const uint32_t w8[8] = {va[q].x, va[q].y, va[q].z, va[q].w,
-                                            vb[q].x, vb[q].y, vb[q].z, vb[q].w};
-#pragma unroll
-                    for (int k = 0; k < 8; ++k)
-#pragma unroll
-                        for (int e = 0; e < 4; ++e)
-                            if ((w8[k] >> (8 * e)) & 0xFFu) m |= 1u << (4 * k + e);
-                } else {
-                    for (uint32_t b = 0; b < 32 && x0 + b < (uint32_t)nx; ++b)
-                        if (occ[c0 + b]) m |= 1u << b;
-                }
-                bits[row * stride + (wd - row * row_words)] = m;
-            }
-        }
-        __syncthreads();
-    }
-    const uint32_t k = blockIdx.x * kSensorThreads + threadIdx.x;
-    if (k >= n_rays) return;
+    const uint32_t k = blockIdx.x * kRaysPerBlock + threadIdx.x / kWave;
+    if (k >= n_rays) return;  // the whole wave
+    const uint32_t lane = (uint32_t)lane_id();
     int px, py;
     ray_target(k, nx, ny, px, py);
     const double sx = (double)nx / 2.0, sy = (double)ny / 2.0;
     const double dx = ((double)px + 0.5) - sx, dy = ((double)py + 0.5) - sy;
-    int ix = (int)floor(sx), iy = (int)floor(sy);
+    const int ix0 = (int)floor(sx), iy0 = (int)floor(sy);
     const int stepx = dx > 0.0 ? 1 : -1, stepy = dy > 0.0 ? 1 : -1;
     const double inf = __builtin_huge_val();
     const double tdx = dx != 0.0 ? fabs(1.0 / dx) : inf;
     const double tdy = dy != 0.0 ? fabs(1.0 / dy) : inf;
-    // ray parameter of the first x and y cell boundaries, and their spacing
-    double tmx = dx > 0.0 ? ((double)(ix + 1) - sx) / dx
-                          : (dx < 0.0 ? ((double)ix - sx) / dx : inf);
-    double tmy = dy > 0.0 ? ((double)(iy + 1) - sy) / dy
-                          : (dy < 0.0 ? ((double)iy - sy) / dy : inf);
-    // one step per iteration with selects instead of branches: a wave runs one ray per lane, so
-    // the loop is bound by its instruction count, not by memory
-    for (int step = 0; step < 2 * (nx + ny); ++step) {
-        const uint32_t c = (uint32_t)iy * (uint32_t)nx + (uint32_t)ix;
-        seen[c] = 1;
-        const bool hit = kLds ? ((bits[(uint32_t)iy * stride + ((uint32_t)ix >> 5)] >> (ix & 31)) & 1u) != 0
-                              : occ[c] != 0;
-        const bool xs = tmx < tmy;
-        const double tmx_n = tmx + tdx, tmy_n = tmy + tdy;
-        const int ixn = xs ? ix + stepx : ix, iyn = xs ? iy : iy + stepy;
-        tmx = xs ? tmx_n : tmx;
-        tmy = xs ? tmy : tmy_n;
-        // bitwise, not short-circuit: every term is one compare, none needs a branch
-        const bool stop = hit | ((ix == px) & (iy == py)) | (ixn < 0) | (ixn >= nx) | (iyn < 0) |
-                          (iyn >= ny);
-        if (stop) break;
-        ix = ixn;
-        iy = iyn;
+    // ray parameter of the first x and y cell boundaries
+    const double tmx = dx > 0.0 ? ((double)(ix0 + 1) - sx) / dx
+                                : (dx < 0.0 ? ((double)ix0 - sx) / dx : inf);
+    const double tmy = dy > 0.0 ? ((double)(iy0 + 1) - sy) / dy
+                                : (dy < 0.0 ? ((double)iy0 - sy) / dy : inf);
+    const uint32_t limit = 2u * (uint32_t)(nx + ny);
+    for (uint32_t base = 0; base < limit; base += kWave) {
+        const uint32_t n = base + lane;
+        const uint32_t i = x_steps(n, tmx, tdx, tmy, tdy);
+        const int ix = ix0 + stepx * (int)i, iy = iy0 + stepy * (int)(n - i);
+        const bool in = n < limit && ix >= 0 && ix < nx && iy >= 0 && iy < ny;
+        const uint32_t c = in ? (uint32_t)iy * (uint32_t)nx + (uint32_t)ix : 0u;
+        const bool ends = !in || occ[c] != 0 || (ix == px && iy == py);
+        const uint64_t enders = __ballot(ends);
+        const uint32_t first = enders ? (uint32_t)(__ffsll((unsigned long long)enders) - 1)
+                                      : (uint32_t)kWave;
+        if (in && lane <= first) seen[c] = 1;
+        if (enders) return;
     }
 }
 
@@ -177,25 +143,6 @@ __global__ __launch_bounds__(kSensorThreads) void k_sensor_detect(
     m_free[c] = mf;
 }
 
-// The rays' bit mask (up to 128 KiB) is above the default dynamic LDS limit: raise it once on
-// every device the library launches on (the attribute is per device).
-hipError_t allow_ray_lds()
-{
-    static std::mutex mu;
-    static std::vector<bool> done;
-    int dev = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e != hipSuccess) return e;
-    std::lock_guard<std::mutex> lock(mu);
-    if ((size_t)dev < done.size() && done[dev]) return hipSuccess;
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sensor_rays<true>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, kRayLdsMax);
-    if (e != hipSuccess) return e;
-    if ((size_t)dev >= done.size()) done.resize(dev + 1, false);
-    done[dev] = true;
-    return hipSuccess;
-}
-
 hipError_t launch_sensor_truth(const double* rects, int n_rects, const uint8_t* static_occ,
                                int nx, int ny, double cell, uint8_t* occ, uint8_t* seen,
                                hipStream_t s)
@@ -214,16 +161,9 @@ hipError_t launch_sensor_scan(const uint8_t* occ, int nx, int ny, bool clear, do
     const uint32_t cblocks = ceil_div(C, kSensorThreads);
     if (clear) DOGM_LAUNCH(k_sensor_clear, dim3(cblocks), dim3(kSensorThreads), 0, s, seen, C);
     const uint32_t n_rays = 2u * (uint32_t)nx + (ny >= 2 ? 2u * (uint32_t)(ny - 2) : 0u);
-    const uint32_t rblocks = ceil_div(n_rays, kSensorThreads);
-    const size_t lds = 4ull * ((((uint32_t)nx + 31u) / 32u) | 1u) * (uint32_t)ny;
-    if (lds <= kRayLdsMax) {
-        if (const hipError_t e = allow_ray_lds(); e != hipSuccess) return e;
-        DOGM_LAUNCH(k_sensor_rays<true>, dim3(rblocks), dim3(kSensorThreads), lds, s, occ, nx, ny,
-                    n_rays, seen);
-    } else {
-        DOGM_LAUNCH(k_sensor_rays<false>, dim3(rblocks), dim3(kSensorThreads), 0, s, occ, nx, ny,
-                    n_rays, seen);
-    }
+    const uint32_t rblocks = ceil_div(n_rays, kRaysPerBlock);
+    DOGM_LAUNCH(k_sensor_rays, dim3(rblocks), dim3(kSensorThreads), 0, s, occ, nx, ny, n_rays,
+                seen);
     if (m_occ && m_free)
         DOGM_LAUNCH(k_sensor_detect, dim3(cblocks), dim3(kSensorThreads), 0, s, occ, seen, C, p_d,
                     p_cl, m_o, m_f, (uint32_t)seed, (uint32_t)(seed >> 32), cycle, m_occ, m_free);

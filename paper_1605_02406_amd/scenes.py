@@ -209,7 +209,10 @@ def make_scene(wl: dict, seed: int | None = None) -> Scene:
 
 def raycast_observed(occ: np.ndarray) -> np.ndarray:
     """Cells seen from the grid centre (bool [ny, nx]): Amanatides-Woo traversal of one ray
-    per perimeter cell centre, stopping at (and including) the first occupied cell."""
+    per perimeter cell centre, stopping at (and including) the first occupied cell.  The i-th
+    boundary crossing along an axis is at t_i = t_0 + i d (one rounded product and one rounded
+    sum in FP64; t_0 itself for i = 0), and each step crosses the nearer boundary, an x boundary
+    only when its crossing is strictly smaller."""
     ny, nx = occ.shape
     sx, sy = nx / 2.0, ny / 2.0  # sensor position in cell units
     per = ([(i, 0) for i in range(nx)] + [(i, ny - 1) for i in range(nx)] +
@@ -226,6 +229,8 @@ def raycast_observed(occ: np.ndarray) -> np.ndarray:
         tdy = np.where(dy != 0, np.abs(1.0 / dy), np.inf)
         tmx = np.where(dx > 0, (ix + 1 - sx) / dx, np.where(dx < 0, (ix - sx) / dx, np.inf))
         tmy = np.where(dy > 0, (iy + 1 - sy) / dy, np.where(dy < 0, (iy - sy) / dy, np.inf))
+    ci = np.zeros(len(per), np.int64)  # x and y boundaries crossed so far
+    cj = np.zeros(len(per), np.int64)
     seen = np.zeros((ny, nx), bool)
     active = np.ones(len(per), bool)
     for _ in range(2 * (nx + ny)):
@@ -240,12 +245,15 @@ def raycast_observed(occ: np.ndarray) -> np.ndarray:
         done = (ix[a] == tx[a] - 0.5) & (iy[a] == ty[a] - 0.5)
         active[a[done]] = False
         a = a[~done]
-        go_x = tmx[a] < tmy[a]
+        with np.errstate(invalid="ignore"):  # 0 * inf for an axis the ray does not move along
+            cx = np.where(ci[a] == 0, tmx[a], tmx[a] + ci[a] * tdx[a])
+            cy = np.where(cj[a] == 0, tmy[a], tmy[a] + cj[a] * tdy[a])
+        go_x = cx < cy
         ax, ay = a[go_x], a[~go_x]
         ix[ax] += stepx[ax]
-        tmx[ax] += tdx[ax]
+        ci[ax] += 1
         iy[ay] += stepy[ay]
-        tmy[ay] += tdy[ay]
+        cj[ay] += 1
         out = (ix[a] < 0) | (ix[a] >= nx) | (iy[a] < 0) | (iy[a] >= ny)
         active[a[out]] = False
         ix[a[out]] = np.clip(ix[a[out]], 0, nx - 1)
