@@ -289,7 +289,10 @@ int dogm_sensor_truth(const double* rects, int32_t n_rects, const uint8_t* stati
 /* dogm_sensor_scan: the cells a sensor at the grid centre (nx/2, ny/2 in cell units) observes,
  * and the evidence masses of one cycle.  One Amanatides-Woo traversal (FP64) per perimeter
  * cell towards that cell's centre marks seen[c] = 1 in every cell it passes up to and
- * including the first cell with occ != 0 (or the perimeter cell); every other cell gets 0.  In
+ * including the first cell with occ != 0 (or the perimeter cell); every other cell gets 0.
+ * The i-th cell boundary crossed along an axis lies at ray parameter t_0 + i d (d = 1 / |the
+ * direction's component|, one rounded product and one rounded sum), and a step crosses an x
+ * boundary only when its parameter is strictly below the next y boundary's.  In
  * each observed cell one Bernoulli draw (Philox4x32-10, key `seed`, counter (c, cycle, 4, 0),
  * uniform as in the filter) detects with probability p_d if occupied and p_cl if free; a
  * detection gives (m_occ, m_free) = (2 P - 1, 0) with P = p_d / (p_d + p_cl), an observed cell

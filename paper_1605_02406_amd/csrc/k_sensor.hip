@@ -3,7 +3,8 @@
 // sensor and filter needs no host work per cycle.
 //
 //  - truth: a cell is occupied when its centre lies in one of the given axis-aligned rectangles
-//    (boxes and walls, bounds included) or in the static occupancy mask (clutter);
+//    (boxes and walls, bounds included) or in the static occupancy mask (clutter): the mask is
+//    copied, then one block per rectangle marks its cells;
 //  - rays: one Amanatides-Woo traversal per perimeter cell, from the sensor at the grid centre
 //    towards that cell's centre, marking every cell it passes up to and including the first
 //    occupied one (or the perimeter cell); the i-th boundary crossing along an axis is at
@@ -20,24 +21,44 @@ constexpr uint32_t kPurposeSensor = 4;
 constexpr int kSensorThreads = 256;
 constexpr int kRaysPerBlock = kSensorThreads / kWave;  // one ray per wave
 
-__global__ __launch_bounds__(kSensorThreads) void k_sensor_truth(const double* rects, int n_rects,
-                                                                 const uint8_t* static_occ,
-                                                                 int nx, int ny, double cell,
-                                                                 uint8_t* occ, uint8_t* seen)
+// Truth, first launch: every cell takes its static occupancy (none without a mask).
+__global__ __launch_bounds__(kSensorThreads) void k_sensor_truth_static(const uint8_t* static_occ,
+                                                                        uint32_t C, uint8_t* occ,
+                                                                        uint8_t* seen)
 {
-    const uint32_t C = (uint32_t)nx * (uint32_t)ny;
     const uint32_t c = blockIdx.x * kSensorThreads + threadIdx.x;
     if (c >= C) return;
-    const uint32_t ix = c % (uint32_t)nx, iy = c / (uint32_t)nx;
-    const double xc = ((double)ix + 0.5) * cell, yc = ((double)iy + 0.5) * cell;
-    bool o = static_occ ? static_occ[c] != 0 : false;
-    for (int r = 0; r < n_rects && !o; ++r) {
-        const double x0 = rects[4 * r], y0 = rects[4 * r + 1];
-        const double x1 = rects[4 * r + 2], y1 = rects[4 * r + 3];
-        o = xc >= x0 && xc <= x1 && yc >= y0 && yc <= y1;
-    }
-    occ[c] = o ? 1 : 0;
+    occ[c] = (static_occ && static_occ[c] != 0) ? 1 : 0;
     if (seen) seen[c] = 0;
+}
+
+// First candidate index of a cell-centre range: centres (i + 1/2) cell for i >= v / cell - 1/2,
+// one cell of margin for the rounding of that estimate, clamped to [0, n].
+__device__ __forceinline__ int centre_index(double v, double cell, int n, int margin)
+{
+    const double e = floor(v / cell - 0.5) + (double)margin;
+    return e < 0.0 ? 0 : (e > (double)n ? n : (int)e);
+}
+
+// Truth, second launch: one block per rectangle marks the cells whose centre lies in it (bounds
+// included), testing every candidate cell with the same FP64 expressions as a test per cell.
+__global__ __launch_bounds__(kSensorThreads) void k_sensor_truth_rects(const double* rects, int nx,
+                                                                       int ny, double cell,
+                                                                       uint8_t* occ)
+{
+    const double x0 = rects[4 * blockIdx.x], y0 = rects[4 * blockIdx.x + 1];
+    const double x1 = rects[4 * blockIdx.x + 2], y1 = rects[4 * blockIdx.x + 3];
+    if (!(x0 <= x1 && y0 <= y1)) return;  // empty, or a coordinate is not a number
+    const int ixa = centre_index(x0, cell, nx, -1), ixb = centre_index(x1, cell, nx, 2);
+    const int iya = centre_index(y0, cell, ny, -1), iyb = centre_index(y1, cell, ny, 2);
+    if (ixa >= ixb || iya >= iyb) return;
+    const uint32_t w = (uint32_t)(ixb - ixa), n = w * (uint32_t)(iyb - iya);
+    for (uint32_t t = threadIdx.x; t < n; t += kSensorThreads) {
+        const int ix = ixa + (int)(t % w), iy = iya + (int)(t / w);
+        const double xc = ((double)ix + 0.5) * cell, yc = ((double)iy + 0.5) * cell;
+        if (xc >= x0 && xc <= x1 && yc >= y0 && yc <= y1)
+            occ[(uint32_t)iy * (uint32_t)nx + (uint32_t)ix] = 1;
+    }
 }
 
 __global__ __launch_bounds__(kSensorThreads) void k_sensor_clear(uint8_t* seen, uint32_t C)
@@ -148,8 +169,11 @@ hipError_t launch_sensor_truth(const double* rects, int n_rects, const uint8_t* 
                                hipStream_t s)
 {
     const uint32_t C = (uint32_t)nx * (uint32_t)ny;
-    DOGM_LAUNCH(k_sensor_truth, dim3(ceil_div(C, kSensorThreads)), dim3(kSensorThreads), 0, s,
-                rects, n_rects, static_occ, nx, ny, cell, occ, seen);
+    DOGM_LAUNCH(k_sensor_truth_static, dim3(ceil_div(C, kSensorThreads)), dim3(kSensorThreads),
+                0, s, static_occ, C, occ, seen);
+    if (n_rects > 0)
+        DOGM_LAUNCH(k_sensor_truth_rects, dim3((uint32_t)n_rects), dim3(kSensorThreads), 0, s,
+                    rects, nx, ny, cell, occ);
     return hipGetLastError();
 }
 

@@ -24,9 +24,36 @@ SCENES = [("small", scenes.WORKLOADS["small"], 3),
                              seed=8), 1)]
 
 
+def truth_edge_cases(s) -> bool:
+    """Rectangles partly or wholly outside the grid, infinite, empty, reversed, not a number,
+    and bounds exactly on cell centres, against the per-cell definition in numpy."""
+    inf, nan = float("inf"), float("nan")
+    nx, ny, cell = 37, 23, 0.2
+    rects = np.array([(-5.0, -5.0, 0.3, 0.3), (0.1, 0.1, 0.1, 0.1), (1e300, 0.0, 1e308, 5.0),
+                      (-inf, 2.1, inf, 2.1), (nan, 0.0, 1.0, 1.0), (3.0, 1.0, 2.0, 4.0),
+                      (0.5, 0.5, 1e308, 1e308), (-inf, -inf, -1.0, inf), (6.9, 4.5, 7.5, 4.5),
+                      (2.3000000000000003, 0.7, 2.9, 1.3)], np.float64)
+    static = (np.arange(nx * ny) % 11 == 0).astype(np.uint8)
+    occ = torch.zeros(nx * ny, dtype=torch.uint8)
+    dogm.sensor_truth(torch.as_tensor(rects), torch.as_tensor(static), nx, ny, cell, occ,
+                      stream=s)
+    xc = (np.arange(nx, dtype=np.float64) + 0.5) * cell
+    yc = (np.arange(ny, dtype=np.float64) + 0.5) * cell
+    ref = static.reshape(ny, nx) != 0
+    for x0, y0, x1, y1 in rects:
+        with np.errstate(invalid="ignore"):
+            ref |= ((yc >= y0) & (yc <= y1))[:, None] & ((xc >= x0) & (xc <= x1))[None, :]
+    ok = np.array_equal(occ.numpy().reshape(ny, nx) != 0, ref)
+    print(f"[emu] truth edge cases {'equal' if ok else 'differ'} ({int(ref.sum())} occupied)",
+          flush=True)
+    return ok
+
+
 def main() -> int:
     dogm.LIB_PATH = build_emu.LIB
     s = HostStream()
+    if not truth_edge_cases(s):
+        return 1
     for name, wl, cycles in SCENES:
         sc = scenes.make_scene(wl, wl.get("seed", 0))
         nx, ny = sc.nx, sc.ny

@@ -77,3 +77,27 @@ def test_device_sensor_rejects_bad_arguments():
         dogm.sensor_scan(occ, 4, 4, 0.01, 0.9, 1, 1, occ, None, None)  # p_D below p_cl
     with pytest.raises(dogm.DogmError):
         dogm.sensor_truth(None, None, 0, 4, 0.2, occ)
+
+
+def test_truth_grid_edge_cases():
+    """Rectangles partly or wholly outside the grid, infinite, empty, reversed, not a number,
+    and bounds exactly on cell centres, against the per-cell definition."""
+    inf, nan = float("inf"), float("nan")
+    nx, ny, cell = 37, 23, 0.2
+    rects = np.array([(-5.0, -5.0, 0.3, 0.3), (0.1, 0.1, 0.1, 0.1), (1e300, 0.0, 1e308, 5.0),
+                      (-inf, 2.1, inf, 2.1), (nan, 0.0, 1.0, 1.0), (3.0, 1.0, 2.0, 4.0),
+                      (0.5, 0.5, 1e308, 1e308), (-inf, -inf, -1.0, inf), (6.9, 4.5, 7.5, 4.5),
+                      (2.3000000000000003, 0.7, 2.9, 1.3)], np.float64)
+    static = (np.arange(nx * ny) % 11 == 0).astype(np.uint8)
+    dev = torch.device("cuda")
+    occ = torch.zeros(nx * ny, dtype=torch.uint8, device=dev)
+    dogm.sensor_truth(torch.as_tensor(rects, device=dev), torch.as_tensor(static, device=dev),
+                      nx, ny, cell, occ)
+    torch.cuda.synchronize()
+    xc = (np.arange(nx, dtype=np.float64) + 0.5) * cell
+    yc = (np.arange(ny, dtype=np.float64) + 0.5) * cell
+    ref = static.reshape(ny, nx) != 0
+    for x0, y0, x1, y1 in rects:
+        with np.errstate(invalid="ignore"):
+            ref |= ((yc >= y0) & (yc <= y1))[:, None] & ((xc >= x0) & (xc <= x1))[None, :]
+    assert np.array_equal(occ.cpu().numpy().reshape(ny, nx) != 0, ref)
