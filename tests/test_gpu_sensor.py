@@ -40,7 +40,10 @@ SCENES = [("small", scenes.WORKLOADS["small"]), ("c512", scenes.WORKLOADS["c512"
           ("90x37", dict(nx=90, ny=37, cell=0.2, scene="boxes", n_boxes=6, clutter=0.02, seed=4)),
           ("1x50", dict(nx=1, ny=50, cell=0.2, scene="boxes", n_boxes=1, clutter=0.1, seed=5)),
           ("50x1", dict(nx=50, ny=1, cell=0.2, scene="boxes", n_boxes=1, clutter=0.1, seed=6)),
-          ("2x2", dict(nx=2, ny=2, cell=0.2, scene="boxes", n_boxes=0, clutter=0.0, seed=7))]
+          ("2x2", dict(nx=2, ny=2, cell=0.2, scene="boxes", n_boxes=0, clutter=0.0, seed=7)),
+          # wider than tall, 6 M cells and 10 000 rays of up to 5 000 steps
+          ("3000x2000", dict(nx=3000, ny=2000, cell=0.1, scene="boxes", n_boxes=60, clutter=0.001,
+                             seed=9))]
 
 
 @pytest.mark.parametrize("name,wl", SCENES, ids=[s[0] for s in SCENES])
