@@ -251,10 +251,11 @@ def approach_profile():
 
 
 def evaluate_approach(p_b: float, n_pers: int = 1 << 19, n_born: int = 1 << 16, seed: int = 0,
-                      model: str = "ds", settle: int = 5) -> dict:
+                      model: str = "ds", settle: int = 5, noise: dict | None = None) -> dict:
     """NEES and velocity error of the approaching object per phase of its profile.  The object
     (1.0 m x 0.8 m) drives along x towards the sensor on the lanes scene; rows of a phase skip
-    its first `settle` cycles only for the rest phase (the filter's start-up)."""
+    its first `settle` cycles only for the rest phase (the filter's start-up).  `noise`
+    overrides filter parameters (e.g. the process noise of the paper's Table I)."""
     import torch
 
     from . import dogm
@@ -264,6 +265,7 @@ def evaluate_approach(p_b: float, n_pers: int = 1 << 19, n_born: int = 1 << 16, 
     obj = scenes.Box(4.0, 0.5 * H + 1.6, 1.0, 0.8, 0.0, 0.0)
     sc.boxes.append(obj)
     filt = dict(scenes.FILTER)
+    filt.update(noise or {})
     filt["p_b"] = p_b
     p = dogm.make_params(sc.nx, sc.ny, sc.cell, n_pers, n_born, seed=seed,
                          model=dogm.MODEL_PHD_MIB if model == "phd" else dogm.MODEL_DS, **filt)
@@ -283,25 +285,31 @@ def evaluate_approach(p_b: float, n_pers: int = 1 << 19, n_born: int = 1 << 16, 
         if phase == "rest" and k <= settle:
             continue
         defined = g.v["mom_flag"].cpu().numpy() != 0
-        S = _box_cells(sc, obj) & defined
-        if not S.any():
-            continue
-        mx = g.v["mean_x"].cpu().numpy()[S].astype(np.float64)
-        vxx = g.v["var_x"].cpu().numpy()[S].astype(np.float64)
-        est, var = cluster_mean(mx), cluster_variance(mx, vxx)
-        rows.append(dict(phase=phase, truth=v, est=est, var=var,
-                         nees=nees(est, var, v) if var > 0 else math.inf))
-    out = {"model": model, "p_b": p_b, "phases": {}}
-    for name, _, _ in APPROACH_PHASES:
-        r = [x for x in rows if x["phase"] == name]
-        if not r:
-            continue
-        nv = np.array([x["nees"] for x in r])
-        err = np.array([x["est"] - x["truth"] for x in r])
-        out["phases"][name] = {"samples": len(r), "nees_mean": float(np.mean(nv)),
-                               "nees_frac_above_95pct": float(np.mean(nv > CHI2_1_95)),
-                               "velocity_error_mean_mps": float(np.mean(err)),
-                               "velocity_sd_mps": float(np.mean([math.sqrt(x["var"]) for x in r]))}
+        detected = np.asarray(obs["det"] if model == "phd" else obs["m_occ"]) > 0
+        mx_all = g.v["mean_x"].cpu().numpy().astype(np.float64)
+        vxx_all = g.v["var_x"].cpu().numpy().astype(np.float64)
+        # two readings of S: every cell of the box with moments, and only those with a detection
+        # in this cycle (the object's returns)
+        for reading, S in (("box", _box_cells(sc, obj) & defined),
+                           ("detected", _box_cells(sc, obj) & defined & detected)):
+            if not S.any():
+                continue
+            est, var = cluster_mean(mx_all[S]), cluster_variance(mx_all[S], vxx_all[S])
+            rows.append(dict(reading=reading, phase=phase, truth=v, est=est, var=var,
+                             nees=nees(est, var, v) if var > 0 else math.inf))
+    out = {"model": model, "p_b": p_b, "noise": {k: filt[k] for k in ("sigma_pos", "sigma_vel")},
+           "phases": {}, "phases_detected_cells": {}}
+    for reading, key in (("box", "phases"), ("detected", "phases_detected_cells")):
+        for name, _, _ in APPROACH_PHASES:
+            r = [x for x in rows if x["phase"] == name and x["reading"] == reading]
+            if not r:
+                continue
+            nv = np.array([x["nees"] for x in r])
+            err = np.array([x["est"] - x["truth"] for x in r])
+            out[key][name] = {"samples": len(r), "nees_mean": float(np.mean(nv)),
+                              "nees_frac_above_95pct": float(np.mean(nv > CHI2_1_95)),
+                              "velocity_error_mean_mps": float(np.mean(err)),
+                              "velocity_sd_mps": float(np.mean([math.sqrt(x["var"]) for x in r]))}
     return out
 
 
@@ -313,11 +321,15 @@ def main():
     ap.add_argument("--model", default="ds,phd", help="ds, phd or both")
     ap.add_argument("--approach", action="store_true",
                     help="the approaching object's phases instead of the lanes metrics")
+    ap.add_argument("--sigma-pos", type=float, default=None, help="process noise, position (m)")
+    ap.add_argument("--sigma-vel", type=float, default=None, help="process noise, velocity (m/s)")
     args = ap.parse_args()
     for model in [m for m in args.model.split(",") if m]:
         for pb in [float(x) for x in args.p_b.split(",") if x]:
             if args.approach:
-                print(json.dumps(evaluate_approach(pb, model=model)), flush=True)
+                noise = {k: v for k, v in (("sigma_pos", args.sigma_pos),
+                                           ("sigma_vel", args.sigma_vel)) if v is not None}
+                print(json.dumps(evaluate_approach(pb, model=model, noise=noise)), flush=True)
             else:
                 print(json.dumps(evaluate(pb, args.cycles, args.warmup, model=model)), flush=True)
 

@@ -71,6 +71,13 @@ def test_constant_velocity_model_lags_the_manoeuvres(approach):
     assert abs(ph["stopped"]["velocity_error_mean_mps"]) < 0.3
 
 
+def test_braking_nees_falls_with_the_birth_probability(approach):
+    # Sec. VIII.B: a low p_B leaves the estimate least able to follow a strong deceleration
+    lo = approach[0.005]["phases_detected_cells"]["decelerate"]["nees_mean"]
+    hi = approach[0.1]["phases_detected_cells"]["decelerate"]["nees_mean"]
+    assert lo > 2.0 * hi
+
+
 def test_births_bias_the_cruising_object_towards_zero(approach):
     lo = approach[0.005]["phases"]["cruise"]["velocity_error_mean_mps"]
     hi = approach[0.1]["phases"]["cruise"]["velocity_error_mean_mps"]
