@@ -135,3 +135,17 @@ def test_degenerate_grid_shapes(nx, ny):
     for k in range(2):
         print(f"[parity] grid {nx}x{ny} cycle {k + 1}", flush=True)
         pc.cycle(device_meas(scenes.random_measurement(nx * ny, 40 + k)))
+
+
+def test_largest_cell_count():
+    """nx * ny = 2^24 - 1 (4095 x 4097, the largest grid the boundary accepts; keys of 24 bits
+    sorted in three passes): one cycle of per-call parity from arbitrary particle states and a
+    random measurement."""
+    nx, ny = 4095, 4097
+    assert nx * ny == (1 << 24) - 1
+    p = dogm.make_params(nx, ny, 0.1, 1 << 20, 1 << 18, seed=9, grid_id=77, **scenes.FILTER)
+    g = dogm.Grid(p)
+    g.load_state(scenes.random_particles(nx, ny, 0.1, 1 << 20, 40, spread=0.3))
+    print("[parity] largest cell count, one cycle", flush=True)
+    PerCall(g).cycle(device_meas(scenes.random_measurement(nx * ny, 91)))
+    assert g.status() & dogm.ST_INTERNAL == 0
