@@ -197,12 +197,16 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(Batch b, uint32_t
     const int lane = lane_id();
     const uint64_t lt_mask = (1ull << lane) - 1ull;
 
-    // LDS: per-wave digit counts (16-bit: at most kSortTile per digit), local digit starts,
-    // global digit offsets, one staging row (kSortTile values of the widest array moved)
-    uint16_t* cnt = reinterpret_cast<uint16_t*>(lds);       // [kSortWaves][nbins]
-    uint32_t* tstart = lds + (kSortWaves * nbins) / 2;      // [nbins]
-    uint32_t* goff = tstart + nbins;                        // [nbins]
-    uint32_t* stage = goff + nbins;                         // [kSortTile]
+    // LDS: per-wave digit counts (16-bit: at most kSortTile per digit), local digit starts
+    // (16-bit), global digit offsets; the staging row (kSortTile values of the widest array
+    // moved) reuses the counters' space once every element's local position is known, which
+    // keeps 11-bit digits within half the LDS of a CU (two blocks per CU)
+    const uint32_t region_words = max((uint32_t)(kSortWaves * nbins) / 2u,
+                                      (uint32_t)(kSortTile * sizeof(R)) / 4u);
+    uint16_t* cnt = reinterpret_cast<uint16_t*>(lds);                      // [kSortWaves][nbins]
+    uint16_t* tstart = reinterpret_cast<uint16_t*>(lds + region_words);    // [nbins]
+    uint32_t* goff = lds + region_words + nbins / 2;                       // [nbins]
+    uint32_t* stage = lds;                                                 // [kSortTile]
 
     for (uint32_t d = threadIdx.x; d < (kSortWaves * nbins) / 2; d += kSortThreads) lds[d] = 0;
     __syncthreads();
@@ -271,7 +275,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(Batch b, uint32_t
         for (int j = 0; j < kMaxDpt; ++j) {
             if ((uint32_t)j >= dpt) break;
             const uint32_t d = d0 + j;
-            tstart[d] = lrun;
+            tstart[d] = (uint16_t)lrun;
             goff[d] = grun + before[j];
             lrun += tot[j];
             grun += gl[j];
@@ -286,11 +290,14 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(Batch b, uint32_t
         lpos[it] = 0xFFFFFFFFu;
         if (rank[it] != 0xFFFFFFFFu) {
             const uint32_t d = (k[it] >> shift) & mask;
-            lpos[it] = tstart[d] + cnt[wave * nbins + d] + rank[it];
-            if (lpos[it] < (uint32_t)kSortTile) stage[lpos[it]] = k[it];
-            else status_or(G, kStInternal);
+            lpos[it] = (uint32_t)tstart[d] + cnt[wave * nbins + d] + rank[it];
+            if (lpos[it] >= (uint32_t)kSortTile) status_or(G, kStInternal);
         }
     }
+    __syncthreads();  // the counters are read: the staging row may overwrite them
+#pragma unroll
+    for (int it = 0; it < kSortItems; ++it)
+        if (lpos[it] < (uint32_t)kSortTile) stage[lpos[it]] = k[it];
     __syncthreads();
     const uint32_t nvalid = min((uint32_t)kSortTile, G.nu - tile * kSortTile);
     uint32_t gpos[kSortItems];
@@ -324,10 +331,9 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(Batch b, uint32_t
     move_out(pa, reinterpret_cast<R*>(A.ow), stage, lpos, gpos);
 }
 
-// The scatter's dynamic LDS (up to 112 KiB with 11-bit digits and FP64 state) is above the
-// default limit: raise it once on every device the library launches on (the attribute is per
-// device).
-constexpr int kScatterLdsMax = 112 * 1024;
+// The scatter's dynamic LDS (76 KiB with 11-bit digits) is above the default limit: raise it
+// once on every device the library launches on (the attribute is per device).
+constexpr int kScatterLdsMax = 80 * 1024;
 hipError_t allow_scatter_lds()
 {
     static std::mutex mu;
@@ -377,9 +383,10 @@ hipError_t launch_sort(const GridRef* g, int n, hipStream_t s)
             make_batch(b, sub, m, [](const GridDev& G) { return xcd_blocks(G.n_sort_tiles); });
         const uint32_t nbins = 1u << maxbits;
         const bool real64 = launch_real64(g, n);
-        const size_t lds = sizeof(uint16_t) * (size_t)kSortWaves * nbins +
-                           sizeof(uint32_t) * 2 * (size_t)nbins +
-                           (real64 ? sizeof(double) : sizeof(uint32_t)) * kSortTile;
+        const size_t counters = sizeof(uint16_t) * (size_t)kSortWaves * nbins;
+        const size_t row = (real64 ? sizeof(double) : sizeof(uint32_t)) * (size_t)kSortTile;
+        const size_t lds = (counters > row ? counters : row) + sizeof(uint16_t) * nbins +
+                           sizeof(uint32_t) * (size_t)nbins;
         if (tiles)
             DOGM_LAUNCH_REAL(real64, "k_sort_scatter", k_sort_scatter, dim3(tiles),
                              dim3(kSortThreads), lds, s, b, pass);
