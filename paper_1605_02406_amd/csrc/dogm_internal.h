@@ -18,6 +18,7 @@ namespace dogm {
 
 constexpr int kMaxBatch = 32;
 constexpr int kWave = 64;
+constexpr int kMaxBlockWaves = 1024 / kWave;  // waves of the largest block
 
 // Philox counter word 2: what a draw is for.
 constexpr uint32_t kModelPhdMib = 1;  // the particle PHD/MIB model of Sec. V (else Sec. VI)
@@ -442,26 +443,43 @@ __device__ __forceinline__ T block_sum(T v, T* lds)
 }
 
 // Sum of the partials part[0..limit) and of all n of them (one value per thread, block-wide).
+// A thread issues up to sixteen loads before it adds, and both sums leave the block in one
+// exchange through LDS.
 __device__ __forceinline__ void partials_before(const GArr<uint64_t>& part, uint32_t n,
-                                                uint32_t limit, uint64_t* tmp, uint64_t* before,
-                                                uint64_t* all)
+                                                uint32_t limit, uint64_t* before, uint64_t* all)
 {
+    constexpr int kLoads = 16;
+    __shared__ uint64_t red[2][kMaxBlockWaves];
     uint64_t bsum = 0, asum = 0;
-    for (uint32_t t0 = threadIdx.x; t0 < n; t0 += 4 * blockDim.x) {
-        uint64_t v[4];
+    for (uint32_t t0 = threadIdx.x; t0 < n; t0 += kLoads * blockDim.x) {
+        uint64_t v[kLoads];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < kLoads; ++u) {
             const uint32_t t = t0 + u * blockDim.x;
             v[u] = t < n ? part[t] : 0;
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < kLoads; ++u) {
             asum += v[u];
             if (t0 + u * blockDim.x < limit) bsum += v[u];
         }
     }
-    *before = block_sum(bsum, tmp);
-    *all = block_sum(asum, tmp);
+    bsum = wave_sum(bsum);
+    asum = wave_sum(asum);
+    const int wave = threadIdx.x / kWave;
+    if (lane_id() == 0) {
+        red[0][wave] = bsum;
+        red[1][wave] = asum;
+    }
+    __syncthreads();
+    uint64_t b = 0, a = 0;
+    for (int w = 0; w < (int)(blockDim.x / kWave); ++w) {
+        b += red[0][w];
+        a += red[1][w];
+    }
+    *before = b;
+    *all = a;
+    __syncthreads();  // the exchange row may be written again
 }
 
 }  // namespace dogm

@@ -248,7 +248,7 @@ __global__ __launch_bounds__(kCellThreads) void k_born_offsets(Batch b, int pref
         before = G.bpart[part];
         Stot = *G.S_fixed;
     } else {
-        partials_before(G.bpart, G.n_cell_parts, part, tmp, &before, &Stot);
+        partials_before(G.bpart, G.n_cell_parts, part, &before, &Stot);
         if (part == 0 && threadIdx.x == 0) *G.S_fixed = Stot;
     }
     const uint64_t q = fixed40(rb);

@@ -69,14 +69,13 @@ __device__ __forceinline__ void load_weights(const GArr<R>& wsrc, uint32_t lbase
 // new-born tiles of kBornTile slots) and in total: from their exclusive prefixes where a scan
 // formed them, else added up by the block (tile 0 then stores the total).
 __device__ __forceinline__ void tile_prefix(const GridView& G, uint32_t limit, int prefixed,
-                                            uint32_t tile, uint64_t* tmp, uint64_t* before,
-                                            uint64_t* W)
+                                            uint32_t tile, uint64_t* before, uint64_t* W)
 {
     if (prefixed) {
         *before = G.rpart[limit];
         *W = *G.W_fixed;
     } else {
-        partials_before(G.rpart, G.n_res_ptiles + G.n_born_parts, limit, tmp, before, W);
+        partials_before(G.rpart, G.n_res_ptiles + G.n_born_parts, limit, before, W);
         if (tile == 0 && threadIdx.x == 0) *G.W_fixed = *W;
     }
 }
@@ -84,7 +83,6 @@ __device__ __forceinline__ void tile_prefix(const GridView& G, uint32_t limit, i
 template <typename R>
 __global__ __launch_bounds__(kResThreads) void k_resample(Batch b, int prefixed)
 {
-    __shared__ uint64_t tmp[kResWaves + 1];
     __shared__ uint64_t wave_tot[kResWaves];  // each wave's weight total
     __shared__ uint32_t first[kResTile + 1];  // first draw of each source of the tile; the end
     const int gi = batch_grid(b);
@@ -114,7 +112,7 @@ __global__ __launch_bounds__(kResThreads) void k_resample(Batch b, int prefixed)
     // joint weight before this tile and in total
     const uint32_t limit = born ? G.n_res_ptiles + t_local * (kResTile / kBornTile) : tile;
     uint64_t before, W;
-    tile_prefix(G, limit, prefixed, tile, tmp, &before, &W);
+    tile_prefix(G, limit, prefixed, tile, &before, &W);
 
     if (W == 0) {  // nothing carries weight: keep the sorted persistent set as it is
         if (!born) {
@@ -210,21 +208,22 @@ __global__ __launch_bounds__(kResThreads) void k_resample(Batch b, int prefixed)
     }
 }
 
-// The same draws written by the lanes that own the sources: each wave walks its own sources'
-// draws in windows of kResWindow, every lane writing the local index of each of its sources into
-// the window's LDS map at the source's draws, then the wave writes the window's outputs in order.
-// Cheaper per output than the binary search when sources receive few draws each; a source with
-// many draws is filled by its one lane.
+// The same draws, each wave writing those of its own sources: it walks them in windows of
+// kResWindow, marks in the window's LDS map where each source's draws begin, fills in the source
+// of every draw with a running maximum over the map, then writes the window's outputs in order.
+// Cheaper per output than the binary search when sources receive few draws each, and a source
+// with many draws costs its wave no more map work than many sources with few.
 constexpr int kResWindow = 1024;  // draws per LDS map window of a wave
+constexpr int kMapPerLane = kResWindow / kWave;  // map entries a lane scans
+static_assert(kMapPerLane == 16, "a lane scans its map entries as two 16-byte vectors");
 
 template <typename R>
 __global__ __launch_bounds__(kResThreads) void k_resample_windowed(Batch b, int prefixed)
 {
     constexpr int kSrc = kResRounds * kWave;  // sources per wave
     static_assert(kSrc <= 65536, "local source indices are 16-bit");
-    __shared__ uint64_t tmp[kResWaves + 1];
     __shared__ uint64_t wave_tot[kResWaves];  // each wave's weight total
-    __shared__ uint16_t srcmap[kResWaves][kResWindow];
+    __shared__ __attribute__((aligned(16))) uint16_t srcmap[kResWaves][kResWindow];
     const int gi = batch_grid(b);
     const GridView G = grid_view(b.g[gi]);
     const uint32_t ntiles = G.n_res_ptiles + G.n_res_btiles;
@@ -251,7 +250,7 @@ __global__ __launch_bounds__(kResThreads) void k_resample_windowed(Batch b, int 
     // joint weight before this tile and in total
     const uint32_t limit = born ? G.n_res_ptiles + t_local * (kResTile / kBornTile) : tile;
     uint64_t before, W;
-    tile_prefix(G, limit, prefixed, tile, tmp, &before, &W);
+    tile_prefix(G, limit, prefixed, tile, &before, &W);
 
     if (W == 0) {  // nothing carries weight: keep the sorted persistent set as it is
         if (!born) {
@@ -311,15 +310,57 @@ __global__ __launch_bounds__(kResThreads) void k_resample_windowed(Batch b, int 
     const auto X = real<R>(G.x), Y = real<R>(G.y), VX = real<R>(G.vx), VY = real<R>(G.vy);
     const auto Wt = real<R>(G.w);
     uint16_t* map = srcmap[wave];
+    u32x4* mine = reinterpret_cast<u32x4*>(map + lane * kMapPerLane);
+    uint32_t carry = 0;  // 1 + local index of the source that holds the window's first draw
     for (uint32_t wb = j_begin; wb < j_end; wb += kResWindow) {
         const uint32_t we = min(wb + (uint32_t)kResWindow, j_end);
+        // the map gets 1 + the local index of every source whose draws start in the window, at
+        // its first draw, and 0 elsewhere; a running maximum over the window then gives every
+        // draw its source (sources ascend with their draws), in the same few steps however the
+        // draws are spread over the sources.  The map is written and read by this wave only.
+        mine[0] = u32x4{0u, 0u, 0u, 0u};
+        mine[1] = u32x4{0u, 0u, 0u, 0u};
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+        __builtin_amdgcn_wave_barrier();
 #pragma unroll
-        for (int r = 0; r < kResRounds; ++r) {
-            const uint32_t lo = j0[r] > wb ? j0[r] : wb;
-            const uint32_t hi = j1[r] < we ? j1[r] : we;
-            for (uint32_t j = lo; j < hi; ++j) map[j - wb] = (uint16_t)(lane * kResRounds + r);
+        for (int r = 0; r < kResRounds; ++r)
+            if (j0[r] < j1[r] && j0[r] >= wb && j0[r] < we)
+                map[j0[r] - wb] = (uint16_t)(lane * kResRounds + r + 1);
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        {
+            const u32x4 h0 = mine[0], h1 = mine[1];
+            uint32_t e[kMapPerLane];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                e[2 * i] = h0[i] & 0xFFFFu;
+                e[2 * i + 1] = h0[i] >> 16;
+                e[8 + 2 * i] = h1[i] & 0xFFFFu;
+                e[8 + 2 * i + 1] = h1[i] >> 16;
+            }
+#pragma unroll
+            for (int i = 1; i < kMapPerLane; ++i) e[i] = e[i] > e[i - 1] ? e[i] : e[i - 1];
+            uint32_t incl = e[kMapPerLane - 1];
+#pragma unroll
+            for (int off = 1; off < kWave; off <<= 1) {
+                const uint32_t o = __shfl_up(incl, off, kWave);
+                if (lane >= off) incl = o > incl ? o : incl;
+            }
+            uint32_t excl = __shfl_up(incl, 1, kWave);
+            excl = lane == 0 ? carry : (excl > carry ? excl : carry);
+            u32x4 o0, o1;
+#pragma unroll
+            for (int i = 0; i < kMapPerLane; ++i) e[i] = e[i] > excl ? e[i] : excl;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                o0[i] = e[2 * i] | (e[2 * i + 1] << 16);
+                o1[i] = e[8 + 2 * i] | (e[8 + 2 * i + 1] << 16);
+            }
+            mine[0] = o0;
+            mine[1] = o1;
+            const uint32_t last = __shfl(incl, kWave - 1, kWave);
+            carry = last > carry ? last : carry;
         }
-        // the map is written and read by this wave only
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
         __builtin_amdgcn_wave_barrier();
         // four outputs per lane per step, their source reads issued together
@@ -330,7 +371,7 @@ __global__ __launch_bounds__(kResThreads) void k_resample_windowed(Batch b, int 
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {
                 const uint32_t j = j0s + u * kWave;
-                src[u] = j < we ? wbase + map[j - wb] : wbase;
+                src[u] = j < we ? wbase + map[j - wb] - 1u : wbase;
             }
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {

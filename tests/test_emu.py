@@ -78,3 +78,12 @@ def test_batched_and_allocation_free_cycles_equal_the_single_cycle(emu_env):
     print(out[-3000:])
     assert r.returncode == 0, out[-6000:]
     assert "shuffles reading an inactive lane 0" in out
+
+
+def test_draws_piled_on_few_sources(emu_env):
+    r = subprocess.run([sys.executable, "-m", "tests.emu.run_draws"], cwd=ROOT, env=emu_env,
+                       capture_output=True, text=True, timeout=900)
+    out = r.stdout + r.stderr
+    print(out[-3000:])
+    assert r.returncode == 0, out[-6000:]
+    assert "shuffles reading an inactive lane 0" in out

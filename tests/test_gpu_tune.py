@@ -41,3 +41,25 @@ def test_tuner_picks_a_candidate():
     plan, report = tune.tune(p, warmup=2, cycles=3)
     assert plan in tune.candidates(p)
     assert len(report) == len(tune.candidates(p)) and all(v > 0 for v in report.values())
+
+
+def test_blocks_adding_many_partials_match_the_scan():
+    """More partial sums than a block reads in one round of loads (4 727 cell blocks of a
+    1100 x 1100 grid; 5 120 resampling tiles of 2^22 + 2^18 particles): the cycle whose consumers
+    add up the partials themselves equals, bit for bit, the one whose kernel scans them first,
+    under both resampling kernels."""
+    nx = 1100
+    wl = dict(nx=nx, ny=nx, cell=0.2, n_pers=1 << 22, n_born=1 << 18, scene="boxes", n_boxes=40,
+              clutter=0.01, seed=3)
+    p = dogm.make_params(nx, nx, wl["cell"], wl["n_pers"], wl["n_born"], seed=5, **scenes.FILTER)
+    seq = [device_meas(m) for m in scenes.measurement_sequence(wl, 2)]
+    for res in (1, 2):
+        grids = [dogm.Grid(tune.with_plan(p, dict(sort_passes=0, scan_parts=s, resample=res)))
+                 for s in (1, 2)]
+        for meas in seq:
+            for g in grids:
+                g.step(meas)
+        torch.cuda.synchronize()
+        for name, t in grids[0].v.items():
+            assert torch.equal(t, grids[1].v[name]), (res, name)
+        del grids
