@@ -184,7 +184,7 @@ GridDev describe(const dogm_params* p, char* base, size_t* bytes)
     double** pd_c[] = {&d.sum_w, &d.sum_wt, &d.mu_A, &d.mu_UA};
     size_t o_pd_c[4];
     for (int i = 0; i < 4; ++i) o_pd_c[i] = L.take(d_c);
-    const size_t o_msum = L.take(5 * d_c);
+    const size_t o_msum = L.take(kCellSums * d_c);
     float** pf_c[] = {&d.m_pO, &d.m_pF, &d.m_O, &d.m_F, &d.rho_b, &d.rho_p, &d.pign,
                       &d.mean_x, &d.mean_y, &d.var_x, &d.var_y, &d.cov_xy};
     size_t o_pf_c[12];

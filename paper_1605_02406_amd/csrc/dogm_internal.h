@@ -47,6 +47,7 @@ constexpr int kCellThreads = 256;
 
 // Segmented per-cell reductions: each wave owns 64 * kSegItems particles.
 constexpr int kSegThreads = 256;
+constexpr int kCellSums = 6;  // FP64 sums per cell without velocity evidence: one 48-byte record
 constexpr int kSegItems = 8;
 constexpr int kSegRange = kWave * kSegItems;                           // 512
 static_assert(kSegItems % 4 == 0, "a lane reads its items as 16-byte vectors");
@@ -116,6 +117,13 @@ struct GArr {
         return *(__attribute__((address_space(1))) const V*)((Byte*)(GlobalPtr<void>)p +
                                                              i * (uint32_t)sizeof(T));
     }
+    template <typename V>
+    __device__ __forceinline__ void store_vec(uint32_t i, const V& v) const
+    {
+        using Byte = __attribute__((address_space(1))) unsigned char;
+        *(__attribute__((address_space(1))) V*)((Byte*)(GlobalPtr<void>)p + i * (uint32_t)sizeof(T)) =
+            v;
+    }
 };
 
 template <template <typename> class P>
@@ -145,7 +153,7 @@ struct GridT {
     // cells
     P<uint32_t> cstart, cend;
     P<double> sum_w, sum_wt;
-    P<double> msum;  // [5][C]: sums of w vx, w vy, w vx^2, w vy^2, w vx vy per cell
+    P<double> msum;  // [C][kCellSums]: per cell the sums of w, w vx, w vy, w vx^2, w vy^2, w vx vy
     P<float> m_pO, m_pF, m_O, m_F, rho_b, rho_p, pign;
     P<double> mu_A, mu_UA;
     P<uint32_t> born_off;

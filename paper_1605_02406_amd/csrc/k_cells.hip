@@ -391,9 +391,11 @@ __global__ __launch_bounds__(kSegThreads) void k_seg_sums(Batch b)
                 v[5] = wd * x * y;
             },
             [&](uint32_t k, const double* v) {
-                G.sum_w[k] = v[0];
-#pragma unroll
-                for (int j = 0; j < 5; ++j) G.msum[(size_t)j * G.C + k] = v[1 + j];
+                // the cell's six sums leave as one contiguous record
+                const uint32_t r = k * kCellSums;
+                G.msum.store_vec<f64x2>(r, f64x2{v[0], v[1]});
+                G.msum.store_vec<f64x2>(r + 2, f64x2{v[2], v[3]});
+                G.msum.store_vec<f64x2>(r + 4, f64x2{v[4], v[5]});
             });
     }
 }
@@ -416,17 +418,28 @@ __global__ __launch_bounds__(kCellThreads) void k_cells(Batch b)
     if (c < G.C) {
         const bool has = G.cend[c] != G.cstart[c];
         double s = 0.0, st = 0.0, m[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-        if (has) {
-            s = G.sum_w[c];
-            if (kAssoc) {
+        if (kAssoc) {
+            if (has) {
+                s = G.sum_w[c];
                 st = G.sum_wt[c];
             } else {
-#pragma unroll
-                for (int j = 0; j < 5; ++j) m[j] = G.msum[(size_t)j * G.C + c];
+                G.sum_w[c] = 0.0;
+                G.sum_wt[c] = 0.0;
             }
         } else {
-            G.sum_w[c] = 0.0;
-            if (kAssoc) G.sum_wt[c] = 0.0;
+            // the record of the per-cell sums (written for cells with particles only)
+            if (has) {
+                const uint32_t r = c * kCellSums;
+                const f64x2 a = G.msum.load_vec<f64x2>(r), b = G.msum.load_vec<f64x2>(r + 2),
+                            d = G.msum.load_vec<f64x2>(r + 4);
+                s = a[0];
+                m[0] = a[1];
+                m[1] = b[0];
+                m[2] = b[1];
+                m[3] = d[0];
+                m[4] = d[1];
+            }
+            G.sum_w[c] = s;
         }
         R rb;
         const double rp = cell_update<R>(G, M, c, s, st, &rb);

@@ -42,7 +42,7 @@ extern "C" int emu_guard_arena(void* arena, size_t bytes)
     add(d.cstart, 4 * C);
     add(d.cend, 4 * C);
     for (const double* p : {d.sum_w, d.sum_wt, d.mu_A, d.mu_UA}) add(p, 8 * C);
-    add(d.msum, 5 * 8 * C);
+    add(d.msum, kCellSums * 8 * C);
     for (const float* p : {d.m_pO, d.m_pF, d.m_O, d.m_F, d.rho_b, d.rho_p, d.pign, d.mean_x,
                            d.mean_y, d.var_x, d.var_y, d.cov_xy})
         add(p, rb * C);
