@@ -59,10 +59,11 @@ KERNEL_SOURCE = {
 }
 
 
-def sort_plan(C: int, max_bits: int = 11):
-    """Digit widths of the radix sort of keys 0..C (the library's plan)."""
+def sort_plan(C: int, max_bits: int = 11, sort_passes: int = 0):
+    """Digit widths of the radix sort of keys 0..C under a launch plan's sort_passes, as the
+    library sets them: the fewest passes of at most max_bits bits, or more, evenly split."""
     kb = max(1, C.bit_length())
-    passes = (kb + max_bits - 1) // max_bits
+    passes = max((kb + max_bits - 1) // max_bits, sort_passes)
     bits, left = [], kb
     for q in range(passes):
         b = (left + (passes - q) - 1) // (passes - q)
@@ -71,21 +72,23 @@ def sort_plan(C: int, max_bits: int = 11):
     return bits
 
 
-def algorithmic_bytes(kernel: str, nu: int, nb: int, C: int) -> float:
+def algorithmic_bytes(kernel: str, nu: int, nb: int, C: int, sort_passes: int = 0) -> float:
     """Algorithmic bytes of ONE launch of `kernel` on one grid (averaged over the launches of a
     cycle where they differ), from per-unit figures: predict reads x, y, vx, vy, w (20 B) and
     writes them and the key (24 B); the
     resampling reads every joint weight (4 B), the state of each chosen source (16 B) and
     writes the 20-byte state of every output; the per-cell pass of the assignment reads the
     sorted key, weight and velocity (16 B per particle) and writes the cell range and six FP64
-    sums per cell (64 B); the cell pass reads ranges, sums, m_F and the measurement (68 B) and
-    writes masses, normalisers and moments (61 B) per cell; the slot offsets read rho_b and
+    sums per cell (56 B); the cell pass reads ranges, sums, m_F and the measurement (68 B) and
+    writes the weight sum, masses, normalisers and moments (73 B) per cell; the row scans read
+    and write every entry of a digit histogram (one per digit and 4096-key tile); the slot
+    offsets read rho_b and
     write o_c (8 B per cell); the tile pass rescales the persistent weights (key and weight
     read, weight written: 12 B per particle) and writes each new-born slot's 25-byte record.
     The sort counts as one ideal pass over the 24-byte record (read and written once: 48 B per
     particle and cycle), shared evenly by its scatter launches; the scan of the partial sums
     reads and writes one 8-byte sum per tile."""
-    bits = sort_plan(C)
+    bits = sort_plan(C, sort_passes=sort_passes)
     if kernel == "k_predict":
         return 44.0 * nu
     if kernel == "k_sort_scatter":
@@ -95,14 +98,14 @@ def algorithmic_bytes(kernel: str, nu: int, nb: int, C: int) -> float:
     if kernel == "k_sort_hist":
         return 4.0 * nu
     if kernel == "k_scan_rows":
-        tiles = -(-nu // 1024)
+        tiles = -(-nu // 4096)
         return 8.0 * sum(1 << b for b in bits) * tiles / len(bits)
     if kernel == "k_seg_sums<false>":
-        return 16.0 * nu + 64.0 * C
+        return 16.0 * nu + 56.0 * C
     if kernel == "k_seg_sums<true>":
         return 16.0 * nu + 16.0 * C
     if kernel in ("k_cells<false>", "k_cells<true>"):
-        return (68.0 + 61.0) * C
+        return (68.0 + 73.0) * C
     if kernel in ("k_resample", "k_resample_windowed"):
         return 4.0 * (nu + nb) + 16.0 * nu + 20.0 * nu
     if kernel == "k_particle_tiles":
@@ -422,7 +425,7 @@ def main():
 
     dom_ms = dom.durations_ms()
     dom_mean_ms = float(np.mean(dom_ms)) if dom_ms else float("nan")
-    dom_bytes = algorithmic_bytes(dominant, nu, nb, C)
+    dom_bytes = algorithmic_bytes(dominant, nu, nb, C, sort_passes=p.sort_passes)
     dom_gbs = dom_bytes / (dom_mean_ms * 1e-3) / 1e9
     traffic = measured_traffic(dominant, args.workload)
 
