@@ -63,3 +63,28 @@ def test_blocks_adding_many_partials_match_the_scan():
         for name, t in grids[0].v.items():
             assert torch.equal(t, grids[1].v[name]), (res, name)
         del grids
+
+
+def test_grids_with_different_plans_share_a_batch():
+    """One launch per kernel for grids whose launch plans differ (two and three sort passes, the
+    partial sums scanned or added up by their consumers, both resampling kernels) gives every
+    grid, bit for bit, the cycles it gets when stepped alone under its own plan."""
+    plans = [dict(sort_passes=2, scan_parts=1, resample=1),
+             dict(sort_passes=3, scan_parts=2, resample=2),
+             dict(sort_passes=0, scan_parts=2, resample=1)]
+    batched, alone, seqs = [], [], []
+    for i, (n, plan) in enumerate(zip((128, 256, 200), plans)):
+        wl = scenes.batch_workload(n, seed=i + 5)
+        p = tune.with_plan(dogm.make_params(n, n, wl["cell"], wl["n_pers"], wl["n_born"],
+                                            seed=9, grid_id=i, **scenes.FILTER), plan)
+        batched.append(dogm.Grid(p))
+        alone.append(dogm.Grid(p))
+        seqs.append([device_meas(m) for m in scenes.measurement_sequence(wl, 3)])
+    for k in range(3):
+        dogm.step_batch(batched, [seq[k] for seq in seqs])
+        for g, seq in zip(alone, seqs):
+            g.step(seq[k])
+    torch.cuda.synchronize()
+    for gb, ga in zip(batched, alone):
+        for name, t in ga.v.items():
+            assert torch.equal(t, gb.v[name]), name
